@@ -1,0 +1,277 @@
+/*
+ * cobs.h -- C ABI of the MI355X (gfx950) COBS query library.
+ *
+ * COBS (Bingmann, Bradley, Gauger, Iqbal, 2019) indexes an ordered collection
+ * of documents, each a set of strings, by the q-grams ("terms") of their
+ * strings (section 2.1).  Each document gets a Bloom filter; the filters are
+ * stored bit-sliced, one row per filter position and one column per document
+ * (section 2.2).  The compact variant sorts documents by their number of
+ * distinct terms and gives every block of B consecutive documents its own
+ * filter size, reducing one large hash modulo each block's size
+ * (sections 2.2, 2.3).  A query hashes its distinct terms, gathers the h rows
+ * of every term in every block, ANDs them, adds the surviving bits into
+ * per-document scores and reports the documents holding at least a fraction
+ * K of the query's distinct terms (section 2.2), or the top-k by score.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns a cobs_status; nothing is thrown across the ABI.  On
+ *    failure cobs_last_error() (thread-local) describes the cause.
+ *  - The caller owns every input buffer.  The library copies what it needs
+ *    and keeps no caller pointer after the call returns.
+ *  - The library owns every handle and every result array; release them with
+ *    the matching *_free call.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls that
+ *    return host results synchronise that stream before returning.
+ *  - All device memory is HBM of the current HIP device at the time of the
+ *    call that creates the object; later calls must run on the same device.
+ *  - Scores are integers; nothing on the path uses floating point except the
+ *    one-time filter sizing on the host.
+ */
+#ifndef COBS_H
+#define COBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    COBS_OK = 0,
+    COBS_EINVAL = 1,      /* malformed argument */
+    COBS_ENOMEM = 2,      /* device or host allocation failed */
+    COBS_EBUDGET = 3,     /* request can never fit the serving memory budget */
+    COBS_EOVERFLOW = 4,   /* a query's distinct terms exceed the score width */
+    COBS_EDEVICE = 5,     /* a HIP runtime call failed */
+    COBS_ECANCELLED = 6,  /* the server stopped before the request ran */
+    COBS_ESTATE = 7       /* call out of order (e.g. insert before plan) */
+} cobs_status;
+
+typedef enum { COBS_TERMS_DNA = 0, COBS_TERMS_BYTES = 1 } cobs_term_kind;
+typedef enum { COBS_MEM_HOST = 0, COBS_MEM_DEVICE = 1 } cobs_mem;
+typedef enum { COBS_MODE_BATCHED = 0, COBS_MODE_PLAIN = 1 } cobs_mode;
+
+/*
+ * Index parameters (sections 2.1-2.3).
+ *  kind       COBS_TERMS_DNA: terms are k-mers over A,C,G,T (either case); a
+ *             window holding any other byte yields no term; q in 1..31.
+ *             COBS_TERMS_BYTES: terms are q consecutive bytes, q in 1..8
+ *             (text is one continuous string, section 2.3).
+ *  canonical  DNA only: a k-mer and its reverse complement are one term
+ *             (section 2.3).
+ *  num_hashes h >= 1 hash functions per filter (section 2.1); h <= 8.
+ *  fpr        target false-positive rate p of one term lookup, 0 < p < 1.
+ *             Block b gets m_b = max(1, ceil(-n_b h / ln(1 - p^(1/h)))) rows,
+ *             n_b the largest distinct-term count in the block (the fixed-h
+ *             inversion of the Bloom false-positive rate of section 2.1).
+ *  block_docs B: 0 builds the classic index (one block, documents in input
+ *             order); B > 0 the compact one (documents sorted by (distinct
+ *             terms, input id), blocks of B, the last one possibly partial).
+ *  seed       hash seed: hash i of term t is mix64(t ^ s_i), s_i the i-th
+ *             output of SplitMix64 started at seed; row = hash mod m_b.
+ */
+typedef struct {
+    uint32_t kind;
+    uint32_t q;
+    uint32_t canonical;
+    uint32_t num_hashes;
+    double fpr;
+    uint32_t block_docs;
+    uint32_t reserved;
+    uint64_t seed;
+} cobs_params;
+
+/*
+ * A run of documents.  Document d (0-based within the run) owns strings
+ * [doc_str[d], doc_str[d+1]); string s is bytes[str_off[s] .. str_off[s+1]).
+ * str_off and doc_str are always host arrays; `bytes` lives in host memory
+ * (mem = COBS_MEM_HOST) or in device memory of the current device
+ * (mem = COBS_MEM_DEVICE).  Offsets are absolute within `bytes`.
+ */
+typedef struct {
+    const uint8_t *bytes;
+    const uint64_t *str_off;
+    const uint64_t *doc_str;
+    uint32_t n_docs;
+    uint32_t mem;
+} cobs_docs;
+
+typedef struct cobs_index cobs_index;
+typedef struct cobs_builder cobs_builder;
+typedef struct cobs_server cobs_server;
+
+/* ---- construction (sections 2.1-2.3) ------------------------------------ */
+
+/*
+ * Build an index over all documents in one call: distinct-term counts, size
+ * sort and block plan, zeroed padded matrix, then one atomic OR per (term,
+ * hash).  Rows of block b are rowstride_b bytes, a multiple of 128; bit j of
+ * a row (document j of the block) is bit j%8 of byte j/8.  Two builds of the
+ * same input give byte-identical matrices.
+ * Errors: EINVAL (parameters), ENOMEM, EDEVICE.
+ */
+cobs_status cobs_build(const cobs_params *params, const cobs_docs *docs,
+                       void *stream, cobs_index **out);
+
+/*
+ * The same construction in passes, for collections that do not fit one call
+ * (documents may be regenerated or streamed between the passes):
+ *   create(n_docs) -> count(run, first) for every run -> plan ->
+ *   insert(run, first) for every run -> finish.
+ * `first` is the collection id of the run's document 0.  Runs may come in any
+ * order but must cover every document once per pass, with identical content
+ * in both passes.  Out-of-order calls return ESTATE.
+ */
+cobs_status cobs_builder_create(const cobs_params *params, uint32_t n_docs,
+                                void *stream, cobs_builder **out);
+cobs_status cobs_builder_count(cobs_builder *b, const cobs_docs *run, uint32_t first);
+cobs_status cobs_builder_plan(cobs_builder *b);
+cobs_status cobs_builder_insert(cobs_builder *b, const cobs_docs *run, uint32_t first);
+cobs_status cobs_builder_finish(cobs_builder *b, cobs_index **out);
+void cobs_builder_free(cobs_builder *b);
+
+void cobs_index_free(cobs_index *ix);
+
+typedef struct {
+    uint32_t n_docs;
+    uint32_t n_blocks;
+    cobs_params params;
+    uint64_t total_bytes;   /* device bytes of the signature matrix */
+} cobs_index_info_t;
+
+cobs_status cobs_index_info(const cobs_index *ix, cobs_index_info_t *info);
+/* Block b: first sorted position, documents, rows m_b, row stride (bytes),
+ * byte offset of the block inside the matrix. */
+cobs_status cobs_index_block(const cobs_index *ix, uint32_t b, uint32_t *first,
+                             uint32_t *docs, uint64_t *rows, uint64_t *stride,
+                             uint64_t *offset);
+/* order[pos] = input id of the document at sorted position pos (host array
+ * of n_docs); distinct-term count per input id into n_terms (may be NULL). */
+cobs_status cobs_index_order(const cobs_index *ix, uint32_t *order, uint64_t *n_terms);
+/* Copy nbytes of the matrix starting at byte offset into host memory. */
+cobs_status cobs_index_read(const cobs_index *ix, uint64_t offset, uint64_t nbytes,
+                            void *host_dst);
+
+/* ---- query (section 2.2) ------------------------------------------------ */
+
+/*
+ * Options of a query batch.
+ *  k_num/k_den  K = k_num / k_den exactly; a document is reported when its
+ *               score >= T = ceil(k_num * l / k_den), l the query's distinct
+ *               terms; a query with l = 0 reports nothing.  k_den > 0.
+ *  topk         0 = every document reaching T; otherwise at most topk of them.
+ *  score_bits   16 or 32: the score width of the request; a query with more
+ *               than 2^score_bits - 1 distinct terms fails with EOVERFLOW.
+ *  mode         COBS_MODE_BATCHED runs the whole batch through one pipeline
+ *               (persistent gather kernel); COBS_MODE_PLAIN runs the same
+ *               pipeline once per query (one query per launch).
+ *  mem          where `bytes` lives (cobs_mem); q_off is always host memory.
+ */
+typedef struct {
+    uint32_t k_num;
+    uint32_t k_den;
+    uint32_t topk;
+    uint32_t score_bits;
+    uint32_t mode;
+    uint32_t mem;
+} cobs_query_opts;
+
+/* Hits of one query, ordered by (score desc, input id asc). */
+typedef struct {
+    uint32_t n;           /* reported documents */
+    uint32_t num_terms;   /* l = distinct terms of the query */
+    uint32_t *doc_id;     /* [n] input ids */
+    uint32_t *score;      /* [n] scores */
+} cobs_hits;
+
+/*
+ * Query n_queries patterns: query i is bytes[q_off[i] .. q_off[i+1]), one
+ * string each.  *out receives a library-owned array of n_queries cobs_hits
+ * (free with cobs_hits_free(*out, n_queries)).
+ * Errors: EINVAL, EOVERFLOW, ENOMEM, EDEVICE.
+ */
+cobs_status cobs_query_batch(cobs_index *ix, const uint8_t *bytes,
+                             const uint64_t *q_off, uint32_t n_queries,
+                             const cobs_query_opts *opts, void *stream,
+                             cobs_hits **out);
+
+/*
+ * Full score vectors: scores[i * n_docs + d] = score of query i for input
+ * document d (host array, caller-owned), num_terms[i] = l of query i.  The
+ * same gather as cobs_query_batch, without threshold or top-k.
+ */
+cobs_status cobs_query_scores(cobs_index *ix, const uint8_t *bytes,
+                              const uint64_t *q_off, uint32_t n_queries,
+                              uint32_t mem, void *stream, uint32_t *scores,
+                              uint32_t *num_terms);
+
+/*
+ * Distinct terms of each query (steps before the gather): terms of query i
+ * go to terms[cap_off[i] ..], cap_off[i] = sum over j < i of
+ * max(0, len_j - q + 1); num_terms[i] receives l.  The order within a query
+ * is unspecified.  Host arrays, caller-owned.
+ */
+cobs_status cobs_query_terms(const cobs_index *ix, const uint8_t *bytes,
+                             const uint64_t *q_off, uint32_t n_queries,
+                             uint32_t mem, void *stream, uint64_t *terms,
+                             uint32_t *num_terms);
+
+void cobs_hits_free(cobs_hits *hits, uint32_t n);
+
+/* ---- serving ------------------------------------------------------------ */
+
+/*
+ * Continuous-batching server over a resident index.  Requests are admitted
+ * while the score memory they reserve (n_docs * 4 bytes each) fits
+ * score_budget_bytes and a batch slot is free; admitted requests are grouped
+ * into device batches, and up to num_streams batches run on the GPU at once,
+ * so requests arriving while others run join the next batch.
+ *  score_budget_bytes  0 = 1/4 of the free device memory at start
+ *  num_streams         concurrent batches in flight (1..8), 0 = 2
+ *  max_batch_queries   0 = 4096
+ *  max_batch_terms     windows per batch before it is cut, 0 = 2^25
+ *  score_bits          16 or 32 (0 = 32)
+ */
+typedef struct {
+    uint64_t score_budget_bytes;
+    uint32_t num_streams;
+    uint32_t max_batch_queries;
+    uint64_t max_batch_terms;
+    uint32_t score_bits;
+    uint32_t reserved;
+} cobs_serve_opts;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, cancelled, batches;
+    uint64_t p50_ns, p99_ns, max_ns;   /* completion - arrival */
+    double queries_per_s, lookups_per_s, wall_s;
+    uint64_t lookups;
+} cobs_serve_stats;
+
+cobs_status cobs_serve(cobs_index *ix, const cobs_serve_opts *opts, cobs_server **out);
+/*
+ * Submit one query (host bytes, copied).  arrival_ns is the request's arrival
+ * on the CLOCK_MONOTONIC clock (0 = now); latency counts from it.  Returns
+ * EBUDGET when the request alone exceeds the budget.
+ */
+cobs_status cobs_submit(cobs_server *s, const uint8_t *query, uint64_t len,
+                        uint32_t k_num, uint32_t k_den, uint32_t topk,
+                        uint64_t arrival_ns, uint64_t *ticket);
+/* Wait for a ticket; *out receives one library-owned cobs_hits (free with
+ * cobs_hits_free(*out, 1)); latency_ns may be NULL. */
+cobs_status cobs_wait(cobs_server *s, uint64_t ticket, cobs_hits **out,
+                      uint64_t *latency_ns);
+/* Drain every admitted request, stop the loop, fill stats, free the server. */
+cobs_status cobs_serve_stop(cobs_server *s, cobs_serve_stats *stats);
+
+/* ---- misc --------------------------------------------------------------- */
+
+const char *cobs_last_error(void);
+/* Monotonic clock in ns, the clock cobs_submit's arrival_ns uses. */
+uint64_t cobs_now_ns(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
