@@ -265,6 +265,40 @@ cobs_status cobs_wait(cobs_server *s, uint64_t ticket, cobs_hits **out,
 /* Drain every admitted request, stop the loop, fill stats, free the server. */
 cobs_status cobs_serve_stop(cobs_server *s, cobs_serve_stats *stats);
 
+/*
+ * Open-loop load generator for measuring served latency.  A native thread
+ * submits query i (bytes[q_off[i] .. q_off[i+1]), host memory) at
+ * start + arrival_ns[i], start being the call time plus 1 ms, with that
+ * scheduled time as its arrival; the caller's thread waits for every request.
+ * latency_ns[i] (completion - scheduled arrival) and n_hits[i] are written
+ * when non-NULL; results are released.  Returns the first error.
+ */
+cobs_status cobs_serve_replay(cobs_server *s, const uint8_t *bytes, const uint64_t *q_off,
+                              uint32_t n, const uint64_t *arrival_ns, uint32_t k_num,
+                              uint32_t k_den, uint32_t topk, uint64_t *latency_ns,
+                              uint32_t *n_hits);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/*
+ * Per-kernel timing of the query path: while enabled, every launch of the
+ * gather kernel (row gather + AND + ADD + threshold/top-k, the dominant
+ * kernel) is bracketed by HIP events recorded on the stream it runs on, and
+ * the elapsed times are accumulated.  Process-wide; costs one event pair per
+ * launch.  cobs_profile_read copies the totals and, if reset != 0, zeroes them.
+ */
+typedef struct {
+    uint64_t launches;
+    double total_ms;
+    double last_ms;
+    uint64_t row_bytes;   /* algorithmic row bytes of those launches:
+                             sum over queries of l * h * (row bytes per term) */
+    uint64_t terms;       /* distinct query terms of those launches */
+} cobs_kernel_timing;
+
+cobs_status cobs_profile(int enable);
+cobs_status cobs_profile_read(cobs_kernel_timing *gather, int reset);
+
 /* ---- misc --------------------------------------------------------------- */
 
 const char *cobs_last_error(void);

@@ -1,0 +1,339 @@
+"""MI355X (gfx950) COBS: compact bit-sliced signature index, query hot path.
+
+Thin ctypes binding over ``libcobs.so`` (C ABI in ``include/cobs.h``).  This
+layer only marshals arguments: every step of construction and query runs in
+the library's HIP kernels.  PyTorch is used, when present, for device memory
+(query bytes already resident in HBM) and for the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcobs.so")
+_lib = None
+_lock = threading.Lock()
+
+OK, EINVAL, ENOMEM, EBUDGET, EOVERFLOW, EDEVICE, ECANCELLED, ESTATE = range(8)
+DNA, BYTES = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+MODE_BATCHED, MODE_PLAIN = 0, 1
+
+
+class CobsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"cobs status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("q", C.c_uint32), ("canonical", C.c_uint32),
+                ("num_hashes", C.c_uint32), ("fpr", C.c_double), ("block_docs", C.c_uint32),
+                ("reserved", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class DocsC(C.Structure):
+    _fields_ = [("bytes", C.c_void_p), ("str_off", C.c_void_p), ("doc_str", C.c_void_p),
+                ("n_docs", C.c_uint32), ("mem", C.c_uint32)]
+
+
+class IndexInfo(C.Structure):
+    _fields_ = [("n_docs", C.c_uint32), ("n_blocks", C.c_uint32), ("params", Params),
+                ("total_bytes", C.c_uint64)]
+
+
+class QueryOpts(C.Structure):
+    _fields_ = [("k_num", C.c_uint32), ("k_den", C.c_uint32), ("topk", C.c_uint32),
+                ("score_bits", C.c_uint32), ("mode", C.c_uint32), ("mem", C.c_uint32)]
+
+
+class Hits(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("num_terms", C.c_uint32),
+                ("doc_id", C.POINTER(C.c_uint32)), ("score", C.POINTER(C.c_uint32))]
+
+
+class ServeOpts(C.Structure):
+    _fields_ = [("score_budget_bytes", C.c_uint64), ("num_streams", C.c_uint32),
+                ("max_batch_queries", C.c_uint32), ("max_batch_terms", C.c_uint64),
+                ("score_bits", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
+                ("cancelled", C.c_uint64), ("batches", C.c_uint64), ("p50_ns", C.c_uint64),
+                ("p99_ns", C.c_uint64), ("max_ns", C.c_uint64), ("queries_per_s", C.c_double),
+                ("lookups_per_s", C.c_double), ("wall_s", C.c_double), ("lookups", C.c_uint64)]
+
+
+class KernelTiming(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("total_ms", C.c_double), ("last_ms", C.c_double),
+                ("row_bytes", C.c_uint64), ("terms", C.c_uint64)]
+
+
+EXPORTS = {
+    "cobs_build": (C.c_int, [C.POINTER(Params), C.POINTER(DocsC), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "cobs_builder_create": (C.c_int, [C.POINTER(Params), C.c_uint32, C.c_void_p,
+                                      C.POINTER(C.c_void_p)]),
+    "cobs_builder_count": (C.c_int, [C.c_void_p, C.POINTER(DocsC), C.c_uint32]),
+    "cobs_builder_plan": (C.c_int, [C.c_void_p]),
+    "cobs_builder_insert": (C.c_int, [C.c_void_p, C.POINTER(DocsC), C.c_uint32]),
+    "cobs_builder_finish": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "cobs_builder_free": (None, [C.c_void_p]),
+    "cobs_index_free": (None, [C.c_void_p]),
+    "cobs_index_info": (C.c_int, [C.c_void_p, C.POINTER(IndexInfo)]),
+    "cobs_index_block": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]),
+    "cobs_index_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cobs_index_read": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p]),
+    "cobs_query_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                                   C.POINTER(QueryOpts), C.c_void_p, C.POINTER(C.POINTER(Hits))]),
+    "cobs_query_scores": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cobs_query_terms": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cobs_hits_free": (None, [C.POINTER(Hits), C.c_uint32]),
+    "cobs_serve": (C.c_int, [C.c_void_p, C.POINTER(ServeOpts), C.POINTER(C.c_void_p)]),
+    "cobs_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
+                              C.c_uint32, C.c_uint64, C.POINTER(C.c_uint64)]),
+    "cobs_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.POINTER(Hits)),
+                            C.POINTER(C.c_uint64)]),
+    "cobs_serve_stop": (C.c_int, [C.c_void_p, C.POINTER(ServeStats)]),
+    "cobs_profile": (C.c_int, [C.c_int]),
+    "cobs_profile_read": (C.c_int, [C.POINTER(KernelTiming), C.c_int]),
+    "cobs_last_error": (C.c_char_p, []),
+    "cobs_now_ns": (C.c_uint64, []),
+}
+
+
+def lib():
+    """Load libcobs.so (built in-tree by __graft_entry__.build()); fails loudly
+    when it is missing -- there is no fallback path."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+            L = C.CDLL(LIB_PATH)
+            for name, (res, args) in EXPORTS.items():
+                f = getattr(L, name)
+                f.restype, f.argtypes = res, args
+            _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise CobsError(status, lib().cobs_last_error().decode(errors="replace"))
+
+
+def _p(a: np.ndarray):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            pass
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _byte_source(data):
+    """(pointer, mem, keepalive) for host numpy/bytes or a torch CUDA uint8 tensor."""
+    if hasattr(data, "is_cuda") and data.is_cuda:
+        return C.c_void_p(data.data_ptr()), MEM_DEVICE, data
+    arr = np.frombuffer(data, np.uint8) if isinstance(data, (bytes, bytearray)) else \
+        np.ascontiguousarray(data, dtype=np.uint8)
+    if arr.size == 0:
+        arr = np.zeros(1, np.uint8)
+    return C.c_void_p(arr.ctypes.data), MEM_HOST, arr
+
+
+def _docs_struct(data, str_off, doc_str):
+    ptr, mem, keep = _byte_source(data)
+    so = np.ascontiguousarray(str_off, dtype=np.uint64)
+    ds = np.ascontiguousarray(doc_str, dtype=np.uint64)
+    d = DocsC(ptr, C.c_void_p(so.ctypes.data), C.c_void_p(ds.ctypes.data), len(ds) - 1, mem)
+    return d, (keep, so, ds)
+
+
+def make_params(kind=DNA, q=31, canonical=True, h=1, p=0.3, B=0, seed=0x5EED) -> Params:
+    return Params(kind, q, int(canonical), h, p, B, 0, seed)
+
+
+class Index:
+    """A COBS index resident in HBM of the current device."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def build(cls, params: Params, data, str_off, doc_str, stream=None) -> "Index":
+        d, keep = _docs_struct(data, str_off, doc_str)
+        h = C.c_void_p()
+        _check(lib().cobs_build(C.byref(params), C.byref(d), _stream(stream), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def build_streamed(cls, params: Params, n_docs: int, runs, stream=None) -> "Index":
+        """runs(pass_no) yields (first, data, str_off, doc_str) for every run of
+        documents; it is called once for the counting pass and once for the
+        insertion pass."""
+        b = C.c_void_p()
+        st = _stream(stream)
+        _check(lib().cobs_builder_create(C.byref(params), n_docs, st, C.byref(b)))
+        try:
+            for first, data, so, ds in runs(0):
+                d, keep = _docs_struct(data, so, ds)
+                _check(lib().cobs_builder_count(b, C.byref(d), first))
+            _check(lib().cobs_builder_plan(b))
+            for first, data, so, ds in runs(1):
+                d, keep = _docs_struct(data, so, ds)
+                _check(lib().cobs_builder_insert(b, C.byref(d), first))
+            h = C.c_void_p()
+            _check(lib().cobs_builder_finish(b, C.byref(h)))
+            return cls(h)
+        finally:
+            lib().cobs_builder_free(b)
+
+    def close(self):
+        if self._h:
+            lib().cobs_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = IndexInfo()
+        _check(lib().cobs_index_info(self._h, C.byref(i)))
+        return dict(n_docs=i.n_docs, n_blocks=i.n_blocks, total_bytes=i.total_bytes)
+
+    def block(self, b: int) -> dict:
+        f, d = C.c_uint32(), C.c_uint32()
+        r, s, o = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(lib().cobs_index_block(self._h, b, C.byref(f), C.byref(d), C.byref(r),
+                                      C.byref(s), C.byref(o)))
+        return dict(first=f.value, docs=d.value, rows=r.value, stride=s.value, offset=o.value)
+
+    def order(self):
+        n = self.info()["n_docs"]
+        order = np.zeros(max(n, 1), np.uint32)
+        nt = np.zeros(max(n, 1), np.uint64)
+        _check(lib().cobs_index_order(self._h, _p(order), _p(nt)))
+        return order[:n], nt[:n]
+
+    def read(self, offset: int, nbytes: int) -> np.ndarray:
+        out = np.zeros(max(nbytes, 1), np.uint8)
+        _check(lib().cobs_index_read(self._h, offset, nbytes, _p(out)))
+        return out[:nbytes]
+
+    def query(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
+              stream=None):
+        """Hits of every query: list of (doc_ids, scores, num_terms)."""
+        ptr, mem, keep = _byte_source(data)
+        qo = np.ascontiguousarray(q_off, dtype=np.uint64)
+        n = len(qo) - 1
+        opts = QueryOpts(k[0], k[1], topk, score_bits, mode, mem)
+        out = C.POINTER(Hits)()
+        _check(lib().cobs_query_batch(self._h, ptr, _p(qo), n, C.byref(opts), _stream(stream),
+                                      C.byref(out)))
+        try:
+            res = []
+            for i in range(n):
+                h = out[i]
+                ids = np.ctypeslib.as_array(h.doc_id, (max(h.n, 1),))[: h.n].copy()
+                sc = np.ctypeslib.as_array(h.score, (max(h.n, 1),))[: h.n].copy()
+                res.append((ids, sc, int(h.num_terms)))
+            return res
+        finally:
+            lib().cobs_hits_free(out, n)
+
+    def scores(self, data, q_off, stream=None):
+        """Full score matrix [n_queries, n_docs] (input ids) and l per query."""
+        ptr, mem, keep = _byte_source(data)
+        qo = np.ascontiguousarray(q_off, dtype=np.uint64)
+        n = len(qo) - 1
+        nd = self.info()["n_docs"]
+        sc = np.zeros((max(n, 1), max(nd, 1)), np.uint32)
+        nt = np.zeros(max(n, 1), np.uint32)
+        _check(lib().cobs_query_scores(self._h, ptr, _p(qo), n, mem, _stream(stream), _p(sc), _p(nt)))
+        return sc[:n, :nd], nt[:n]
+
+    def terms(self, data, q_off, q: int, stream=None):
+        """Distinct terms of each query (unordered within a query)."""
+        ptr, mem, keep = _byte_source(data)
+        qo = np.ascontiguousarray(q_off, dtype=np.uint64)
+        n = len(qo) - 1
+        lens = np.diff(qo.astype(np.int64))
+        nw = np.maximum(lens - q + 1, 0)
+        base = np.concatenate([[0], np.cumsum(nw)]).astype(np.int64)
+        t = np.zeros(max(int(base[-1]), 1), np.uint64)
+        nt = np.zeros(max(n, 1), np.uint32)
+        _check(lib().cobs_query_terms(self._h, ptr, _p(qo), n, mem, _stream(stream), _p(t), _p(nt)))
+        return [t[base[i]:base[i] + nt[i]].copy() for i in range(n)]
+
+
+class Server:
+    """Continuous-batching server over a resident index (cobs_serve)."""
+
+    def __init__(self, index: Index, budget_bytes=0, num_streams=0, max_batch_queries=0,
+                 max_batch_terms=0, score_bits=32):
+        self.index = index
+        opts = ServeOpts(budget_bytes, num_streams, max_batch_queries, max_batch_terms,
+                         score_bits, 0)
+        self._h = C.c_void_p()
+        _check(lib().cobs_serve(index._h, C.byref(opts), C.byref(self._h)))
+
+    def submit(self, query: bytes, k=(4, 5), topk=0, arrival_ns=0) -> int:
+        arr = np.frombuffer(query, np.uint8) if len(query) else np.zeros(1, np.uint8)
+        t = C.c_uint64()
+        _check(lib().cobs_submit(self._h, C.c_void_p(arr.ctypes.data), len(query), k[0], k[1],
+                                 topk, arrival_ns, C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int):
+        out = C.POINTER(Hits)()
+        lat = C.c_uint64()
+        _check(lib().cobs_wait(self._h, ticket, C.byref(out), C.byref(lat)))
+        try:
+            h = out[0]
+            ids = np.ctypeslib.as_array(h.doc_id, (max(h.n, 1),))[: h.n].copy()
+            sc = np.ctypeslib.as_array(h.score, (max(h.n, 1),))[: h.n].copy()
+            return ids, sc, int(h.num_terms), lat.value
+        finally:
+            lib().cobs_hits_free(out, 1)
+
+    def stop(self) -> dict:
+        st = ServeStats()
+        _check(lib().cobs_serve_stop(self._h, C.byref(st)))
+        self._h = None
+        return {f: getattr(st, f) for f, _ in ServeStats._fields_}
+
+
+def now_ns() -> int:
+    return int(lib().cobs_now_ns())
+
+
+def profile(enable: bool) -> None:
+    """Time every gather-kernel launch with HIP events on its own stream."""
+    _check(lib().cobs_profile(1 if enable else 0))
+
+
+def profile_read(reset: bool = False) -> dict:
+    t = KernelTiming()
+    _check(lib().cobs_profile_read(C.byref(t), 1 if reset else 0))
+    return {f: getattr(t, f) for f, _ in KernelTiming._fields_}

@@ -1,0 +1,138 @@
+// Device-side data layouts and kernel launchers of the COBS query library.
+// Host code (lib.cpp, serve.cpp) calls only these launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cobs {
+
+constexpr int kMaxHashes = 8;
+constexpr uint64_t kInvalidTerm = ~0ull;   // DNA window with a non-ACGT byte
+constexpr uint32_t kSliceBytes = 1024;     // one wavefront: 64 lanes x 16 bytes
+constexpr uint32_t kLdsTableSlots = 8192;  // dedup table held in LDS (64 KiB)
+constexpr uint32_t kSortRun = 2048;        // candidates sorted in LDS per run
+
+struct Seeds {
+    uint64_t s[kMaxHashes];
+};
+
+struct TermSpec {
+    uint32_t kind;       // 0 DNA, 1 BYTES
+    uint32_t q;
+    uint32_t canonical;
+    uint32_t h;
+};
+
+// One wavefront-wide column slice of one block: up to 8192 documents.
+struct SliceDesc {
+    uint64_t base;     // byte offset of (row 0, first byte of the slice)
+    uint32_t stride;   // row stride of the block in bytes
+    uint32_t rows;     // m_b
+    uint32_t width;    // bytes of the slice (multiple of 16, <= 1024)
+    uint32_t ndocs;    // documents in the slice
+    uint32_t doc0;     // sorted position of the slice's first document
+    uint32_t block;
+};
+
+// Per-query state filled by the plan kernel.
+struct QInfo {
+    uint64_t hbase;    // first unique term of the query in the term arrays
+    uint32_t ell;      // distinct terms
+    uint32_t nch;      // term chunks
+    uint32_t pbase;    // first partial slot (multi-chunk queries)
+    uint32_t thr;      // T = ceil(k_num * ell / k_den); > ell means none
+};
+
+// Per-string descriptor used by the build kernels.
+struct StrDesc {
+    uint64_t byte_off;   // offset of the string in the byte buffer
+    uint64_t wbase;      // first window of the string in the run
+    uint32_t doc;        // document index within the piece
+    uint32_t pad;
+};
+
+// Per-document placement used by the insert kernel.
+struct DocPos {
+    uint64_t block_off;  // byte offset of the block
+    uint32_t rows;
+    uint32_t stride;
+    uint32_t col;        // column (position within the block)
+    uint32_t pad;
+};
+
+struct GatherArgs {
+    const uint8_t *matrix;
+    const SliceDesc *slices;
+    const uint32_t *order;
+    const uint64_t *hashes;
+    const QInfo *qinfo;
+    const uint32_t *chunk_prefix;      // [n_queries + 1]
+    const uint64_t *total_items;       // device scalar
+    unsigned long long *work_counter;  // device scalar
+    uint32_t *tickets;                 // [n_queries * n_slices]
+    uint32_t *partials;
+    unsigned long long *cand_counter;  // device scalar
+    uint64_t *cand_key;                // (score << 32) | ~input_id
+    uint32_t *cand_q;
+    uint32_t *qcount;                  // [n_queries] candidates per query
+    uint32_t *full_scores;             // optional [n_queries * n_docs]
+    uint64_t cand_cap;
+    uint32_t n_queries, n_slices, h, chunk, topk, n_docs;
+};
+
+// ---- query path ----------------------------------------------------------
+
+// a1: one term per window of every query (kInvalidTerm for DNA windows with
+// a non-ACGT byte).  qstart[i]: first byte of query i; wbase[i]: first window.
+hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const uint64_t *wbase,
+                          uint32_t n_queries, uint64_t total_windows, TermSpec ts,
+                          uint64_t *terms, hipStream_t st);
+
+// a2+a3: per-query set of terms (hash-set dedup, LDS or global table) and the
+// h hashes of each distinct term.  tbase[i]: the query's global table (used
+// when its table does not fit kLdsTableSlots).
+hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint64_t *tbase,
+                        uint64_t *table, uint64_t *uterms, uint64_t *hashes, uint32_t *nterms,
+                        uint32_t n_queries, TermSpec ts, Seeds seeds, hipStream_t st);
+uint64_t dedup_table_cap(uint64_t windows);   // slots of a query's table
+// tickets: [n_queries * n_slices], zero before the first gather; every
+// complete gather launch leaves them zero again.
+
+// Per-query chunks, thresholds, partial slots, work totals; zeroes counters.
+hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, uint32_t n_queries,
+                       uint32_t chunk, uint32_t n_slices, uint32_t k_num, uint32_t k_den,
+                       uint64_t ell_limit, QInfo *qinfo, uint32_t *chunk_prefix,
+                       uint64_t *total_items, unsigned long long *work_counter,
+                       unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags,
+                       hipStream_t st);
+
+// a5-a8: persistent gather / AND / ADD / threshold-or-top-k kernel.
+hipError_t launch_gather(const GatherArgs &a, int planes, int grid, hipStream_t st);
+int gather_planes_for(uint64_t max_terms);   // template plane count to use
+int gather_grid(int planes, int h);           // persistent grid size
+
+// a8+a9 ordering: group candidates by query and sort each query's segment by
+// (score desc, input id asc); write the first min(count, topk) hits.
+hipError_t launch_group_sort(const uint64_t *cand_key, const uint32_t *cand_q,
+                             const unsigned long long *n_cand, uint64_t cap,
+                             uint32_t n_queries, uint32_t topk,
+                             const uint32_t *qcount, uint32_t *qstart, uint32_t *qcursor,
+                             uint64_t *seg_a, uint64_t *seg_b, uint32_t *out_start,
+                             uint32_t *out_n, uint32_t *out_id, uint32_t *out_score,
+                             hipStream_t st);
+
+// ---- construction ------------------------------------------------------------
+
+hipError_t launch_count(const uint8_t *bytes, const StrDesc *strs, uint32_t n_strs,
+                        uint64_t total_windows, const uint64_t *tbase, const uint32_t *tlog2,
+                        uint64_t *table, uint32_t *empty_flag, unsigned long long *counts,
+                        TermSpec ts, hipStream_t st);
+
+hipError_t launch_insert(const uint8_t *bytes, const StrDesc *strs, uint32_t n_strs,
+                         uint64_t total_windows, const DocPos *pos, uint32_t *matrix,
+                         TermSpec ts, Seeds seeds, hipStream_t st);
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st);
+
+}  // namespace cobs

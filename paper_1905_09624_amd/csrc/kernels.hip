@@ -1,0 +1,878 @@
+// HIP kernels of the COBS query and construction paths for gfx950 (CDNA4).
+//
+// Query path (section 2.2 of the COBS paper):
+//   extract  -- one q-gram per window (section 2.1), canonical k-mers (2.3)
+//   dedup    -- the query's term set G_q(P), l = |G_q(P)|, h hashes per term
+//   plan     -- per-query term chunks, threshold T = ceil(K l)
+//   gather   -- persistent wavefronts: for each (query, column slice, chunk)
+//               fetch the h rows of every term (one coalesced 1 KiB line per
+//               row slice), AND them, add the surviving bits into bit-plane
+//               counters held in VGPRs; merge chunk partials; threshold or
+//               per-slice top-k; emit candidates
+//   group/sort -- order each query's hits by (score desc, input id asc)
+// Construction (sections 2.1-2.3): exact distinct-term counts per document
+// (hash-set), then one atomic OR per (term, hash) into the padded matrix.
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+namespace cobs {
+namespace {
+
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    // SplitMix64 output finaliser (Steele, Lea, Flood 2014)
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Term of the window starting at s.  DNA: 2-bit codes, first base most
+// significant; the code of an upper-cased A/C/G/T byte u is ((u>>1)^(u>>2))&3.
+__device__ __forceinline__ uint64_t window_term(const uint8_t *s, const TermSpec ts, bool &ok)
+{
+    uint64_t t = 0;
+    if (ts.kind == 1) {
+        for (uint32_t j = 0; j < ts.q; ++j) t |= (uint64_t)s[j] << (8 * j);
+        ok = true;
+        return t;
+    }
+    uint64_t rc = 0;
+    bool valid = true;
+    for (uint32_t j = 0; j < ts.q; ++j) {
+        const uint32_t u = s[j] & 0xDFu;
+        valid &= (u == 'A') | (u == 'C') | (u == 'G') | (u == 'T');
+        const uint32_t c = ((u >> 1) ^ (u >> 2)) & 3u;
+        t = (t << 2) | c;
+        rc |= (uint64_t)(3u - c) << (2 * j);
+    }
+    ok = valid;
+    if (ts.canonical && rc < t) t = rc;
+    return t;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// sum over the 64 lanes (every lane must be active); result is uniform
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v)
+{
+    const uint32_t lane = lane_id();
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    return x - v;
+}
+
+// largest i in [0, n) with a[i] <= v, given a[0] <= v < a[n]
+template <typename T>
+__device__ __forceinline__ uint32_t bsearch_le(const T *a, uint32_t n, uint64_t v)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)a[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__host__ __device__ __forceinline__ uint64_t table_cap(uint64_t n)
+{
+    uint64_t c = 1;
+    while (c < 2 * n) c <<= 1;
+    return c;
+}
+
+// ---- a1: term extraction ------------------------------------------------------
+
+__global__ void extract_kernel(const uint8_t *bytes, const uint64_t *qstart,
+                               const uint64_t *wbase, uint32_t n, uint64_t W, TermSpec ts,
+                               uint64_t *terms)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < W; w += stride) {
+        const uint32_t qi = bsearch_le(wbase, n, w);
+        bool ok;
+        const uint64_t t = window_term(bytes + qstart[qi] + (w - wbase[qi]), ts, ok);
+        terms[w] = ok ? t : kInvalidTerm;
+    }
+}
+
+// ---- a2 + a3: per-query term set and hashes ----------------------------------------
+
+template <bool kLds>
+__device__ __forceinline__ bool set_insert(uint64_t *table, uint64_t cap, uint64_t t,
+                                           uint64_t slot, uint32_t *empty_flag)
+{
+    if (t == kEmpty) return atomicOr(empty_flag, 1u) == 0;
+    for (;;) {
+        const unsigned long long old =
+            atomicCAS((unsigned long long *)&table[slot], (unsigned long long)kEmpty,
+                      (unsigned long long)t);
+        if (old == kEmpty) return true;
+        if (old == t) return false;
+        slot = (slot + 1) & (cap - 1);
+    }
+}
+
+template <bool kLds>
+__device__ void dedup_body(uint64_t *table, uint64_t cap, const uint64_t *terms, uint64_t w0,
+                           uint64_t nw, uint64_t *uterms, uint64_t *hashes, TermSpec ts,
+                           const Seeds &seeds, uint32_t *lcount, uint32_t *lflag)
+{
+    for (uint64_t s = threadIdx.x; s < cap; s += blockDim.x) table[s] = kEmpty;
+    __syncthreads();
+    for (uint64_t w = threadIdx.x; w < nw; w += blockDim.x) {
+        const uint64_t t = terms[w0 + w];
+        if (ts.kind == 0 && t == kInvalidTerm) continue;
+        uint64_t hs[kMaxHashes];
+#pragma unroll
+        for (int i = 0; i < kMaxHashes; ++i)
+            if (i < (int)ts.h) hs[i] = mix64(t ^ seeds.s[i]);
+        if (set_insert<kLds>(table, cap, t, hs[0] & (cap - 1), lflag)) {
+            const uint32_t pos = atomicAdd(lcount, 1u);
+            uterms[w0 + pos] = t;
+#pragma unroll
+            for (int i = 0; i < kMaxHashes; ++i)
+                if (i < (int)ts.h) hashes[(w0 + pos) * ts.h + i] = hs[i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void dedup_kernel(const uint64_t *terms, const uint64_t *wbase,
+                                                    const uint64_t *tbase, uint64_t *gtable,
+                                                    uint64_t *uterms, uint64_t *hashes,
+                                                    uint32_t *nterms, TermSpec ts, Seeds seeds)
+{
+    __shared__ uint64_t ltable[kLdsTableSlots];
+    __shared__ uint32_t lcount, lflag;
+    const uint32_t qi = blockIdx.x;
+    const uint64_t w0 = wbase[qi], nw = wbase[qi + 1] - w0;
+    if (threadIdx.x == 0) { lcount = 0; lflag = 0; }
+    __syncthreads();
+    const uint64_t cap = table_cap(nw);
+    if (cap <= kLdsTableSlots)
+        dedup_body<true>(ltable, cap, terms, w0, nw, uterms, hashes, ts, seeds, &lcount, &lflag);
+    else
+        dedup_body<false>(gtable + tbase[qi], cap, terms, w0, nw, uterms, hashes, ts, seeds,
+                          &lcount, &lflag);
+    __syncthreads();
+    if (threadIdx.x == 0) nterms[qi] = lcount;
+}
+
+// ---- plan ------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, const uint64_t *wbase,
+                                                    uint32_t n, uint32_t chunk, uint32_t n_slices,
+                                                    uint32_t k_num, uint32_t k_den,
+                                                    uint64_t ell_limit, QInfo *qinfo,
+                                                    uint32_t *chunk_prefix, uint64_t *total_items,
+                                                    unsigned long long *work_counter,
+                                                    unsigned long long *cand_counter,
+                                                    uint32_t *qcount, uint32_t *flags)
+{
+    __shared__ uint32_t s_ch[1024], s_ps[1024];
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t per = (n + nt - 1) / nt;
+    const uint32_t a = min(n, tid * per), b = min(n, a + per);
+    uint32_t sc = 0, sp = 0;
+    for (uint32_t q = a; q < b; ++q) {
+        const uint32_t ell = nterms[q];
+        const uint32_t nch = ell ? (ell + chunk - 1) / chunk : 0;
+        sc += nch;
+        sp += nch > 1 ? nch : 0;
+    }
+    s_ch[tid] = sc;
+    s_ps[tid] = sp;
+    __syncthreads();
+    for (uint32_t o = 1; o < nt; o <<= 1) {   // inclusive Hillis-Steele scan
+        uint32_t x = 0, y = 0;
+        if (tid >= o) { x = s_ch[tid - o]; y = s_ps[tid - o]; }
+        __syncthreads();
+        s_ch[tid] += x;
+        s_ps[tid] += y;
+        __syncthreads();
+    }
+    uint32_t cbase = s_ch[tid] - sc, pbase = s_ps[tid] - sp;
+    uint32_t bad = 0;
+    for (uint32_t q = a; q < b; ++q) {
+        const uint32_t ell = nterms[q];
+        const uint32_t nch = ell ? (ell + chunk - 1) / chunk : 0;
+        const uint64_t thr = ((uint64_t)k_num * ell + k_den - 1) / k_den;
+        QInfo qi;
+        qi.hbase = wbase[q];
+        qi.ell = ell;
+        qi.nch = nch;
+        qi.pbase = nch > 1 ? pbase : 0xFFFFFFFFu;
+        qi.thr = thr > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)thr;
+        qinfo[q] = qi;
+        chunk_prefix[q] = cbase;
+        qcount[q] = 0;
+        cbase += nch;
+        pbase += nch > 1 ? nch : 0;
+        bad |= (uint64_t)ell > ell_limit;
+    }
+    if (bad) atomicOr(flags, 1u);
+    if (tid == nt - 1) {
+        chunk_prefix[n] = s_ch[nt - 1];
+        *total_items = (uint64_t)s_ch[nt - 1] * n_slices;
+        *work_counter = 0;
+        *cand_counter = 0;
+    }
+}
+
+// ---- a5-a8: gather / AND / ADD / threshold-or-top-k -------------------------------------
+
+// bit-sliced counter: L holds a 4-bit low part (at most 15 adds between
+// flushes), H the P-bit total; each lane owns 4 dwords = 128 documents
+template <int P>
+struct Counter {
+    uint32_t H[P][4];
+    uint32_t L[4][4];
+    uint32_t n;
+
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int d = 0; d < 4; ++d) H[p][d] = 0;
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int d = 0; d < 4; ++d) L[p][d] = 0;
+        n = 0;
+    }
+
+    __device__ __forceinline__ void flush()
+    {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t h = H[p][d], l = L[p][d], x = h ^ l;
+                H[p][d] = x ^ c;
+                c = (h & l) | (c & x);
+                L[p][d] = 0;
+            }
+#pragma unroll
+            for (int p = 4; p < P; ++p) {
+                const uint32_t h = H[p][d];
+                H[p][d] = h ^ c;
+                c = h & c;
+            }
+        }
+        n = 0;
+    }
+
+    // add one indicator vector (1 bit per document)
+    __device__ __forceinline__ void add(const uint32_t x[4])
+    {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t c = x[d], t;
+            t = L[0][d] & c; L[0][d] ^= c; c = t;
+            t = L[1][d] & c; L[1][d] ^= c; c = t;
+            t = L[2][d] & c; L[2][d] ^= c; c = t;
+            L[3][d] ^= c;
+        }
+        if (++n == 15) flush();
+    }
+
+    // add another full P-bit counter y (plane p, dword d)
+    __device__ __forceinline__ void add_planes(const uint4 *y)
+    {
+        uint32_t Y[P][4];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const uint4 v = y[p * 64];
+            Y[p][0] = v.x; Y[p][1] = v.y; Y[p][2] = v.z; Y[p][3] = v.w;
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const uint32_t h = H[p][d], l = Y[p][d], x = h ^ l;
+                H[p][d] = x ^ c;
+                c = (h & l) | (c & x);
+            }
+        }
+    }
+
+    // documents with score >= T (T < 2^P)
+    __device__ __forceinline__ void ge(uint32_t T, uint32_t out[4]) const
+    {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t gt = 0, eq = ~0u;
+#pragma unroll
+            for (int p = P - 1; p >= 0; --p) {
+                if ((T >> p) & 1u) {
+                    eq &= H[p][d];
+                } else {
+                    gt |= eq & H[p][d];
+                    eq &= ~H[p][d];
+                }
+            }
+            out[d] = gt | eq;
+        }
+    }
+
+    __device__ __forceinline__ uint32_t score(int d, int bit) const
+    {
+        uint32_t s = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) s |= ((H[p][d] >> bit) & 1u) << p;
+        return s;
+    }
+};
+
+template <int P, bool kH1>
+__global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t total = *a.total_items;
+    const uint32_t tchunks = a.chunk_prefix[a.n_queries];
+    constexpr int U = kH1 ? 8 : 4;
+    Counter<P> cnt;
+
+    for (;;) {
+        uint64_t item = 0;
+        if (lane == 0) item = atomicAdd(a.work_counter, 1ull);
+        item = bcast64(item);
+        if (item >= total) break;
+        const uint32_t sl = (uint32_t)(item / tchunks);
+        const uint32_t c = (uint32_t)(item - (uint64_t)sl * tchunks);
+        const uint32_t qi = bsearch_le(a.chunk_prefix, a.n_queries, c);
+        const uint32_t chunk = c - a.chunk_prefix[qi];
+        const QInfo qn = a.qinfo[qi];
+        const SliceDesc sd = a.slices[sl];
+        const uint32_t kbeg = chunk * a.chunk;
+        const uint32_t kend = min(qn.ell, kbeg + a.chunk);
+        const bool act = lane * 16u < sd.width;
+        const uint8_t *mb = a.matrix + sd.base + lane * 16u;
+        const uint64_t *hp = a.hashes + qn.hbase * a.h;
+
+        cnt.clear();
+        for (uint32_t k0 = kbeg; k0 < kend; k0 += 64) {
+            const uint32_t n = min(64u, kend - k0);
+            uint32_t r[kH1 ? 1 : kMaxHashes];
+            if (lane < n) {
+                if (kH1) {
+                    r[0] = (uint32_t)(hp[k0 + lane] % sd.rows);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kMaxHashes; ++i)
+                        if (i < (int)a.h) r[i] = (uint32_t)(hp[(uint64_t)(k0 + lane) * a.h + i] % sd.rows);
+                }
+            }
+            for (uint32_t j = 0; j < n; j += U) {
+                uint32_t x[U][4];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (j + u < n) {
+                        if (kH1) {
+                            const uint32_t row = __builtin_amdgcn_readlane(r[0], j + u);
+                            uint4 v = make_uint4(0, 0, 0, 0);
+                            if (act) v = *(const uint4 *)(mb + (uint64_t)row * sd.stride);
+                            x[u][0] = v.x; x[u][1] = v.y; x[u][2] = v.z; x[u][3] = v.w;
+                        } else {
+                            x[u][0] = x[u][1] = x[u][2] = x[u][3] = ~0u;
+#pragma unroll
+                            for (int i = 0; i < kMaxHashes; ++i) {
+                                if (i < (int)a.h) {
+                                    const uint32_t row = __builtin_amdgcn_readlane(r[i], j + u);
+                                    uint4 v = make_uint4(0, 0, 0, 0);
+                                    if (act) v = *(const uint4 *)(mb + (uint64_t)row * sd.stride);
+                                    x[u][0] &= v.x; x[u][1] &= v.y; x[u][2] &= v.z; x[u][3] &= v.w;
+                                }
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (j + u < n) cnt.add(x[u]);
+            }
+        }
+        if (cnt.n) cnt.flush();
+
+        // several chunks of one (query, slice): the last to finish merges
+        if (qn.nch > 1) {
+            const uint64_t plane_words = (uint64_t)P * 256;
+            uint4 *mine = (uint4 *)(a.partials +
+                                    ((uint64_t)(qn.pbase + chunk) * a.n_slices + sl) * plane_words);
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                mine[p * 64 + lane] = make_uint4(cnt.H[p][0], cnt.H[p][1], cnt.H[p][2], cnt.H[p][3]);
+            __threadfence();
+            uint32_t tk = 0;
+            if (lane == 0) tk = atomicAdd(&a.tickets[(uint64_t)qi * a.n_slices + sl], 1u);
+            tk = __builtin_amdgcn_readfirstlane(tk);
+            if (tk != qn.nch - 1) continue;
+            __threadfence();
+            if (lane == 0) a.tickets[(uint64_t)qi * a.n_slices + sl] = 0;   // ready for reuse
+            for (uint32_t c2 = 0; c2 < qn.nch; ++c2) {
+                if (c2 == chunk) continue;
+                const uint4 *other = (const uint4 *)(a.partials +
+                                     ((uint64_t)(qn.pbase + c2) * a.n_slices + sl) * plane_words);
+                cnt.add_planes(other + lane);
+            }
+        }
+
+        // a8: report this slice of the query
+        uint32_t valid[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const uint32_t b0 = lane * 128u + d * 32u;
+            valid[d] = b0 >= sd.ndocs ? 0u : (sd.ndocs - b0 >= 32 ? ~0u : ((1u << (sd.ndocs - b0)) - 1u));
+        }
+        if (a.full_scores) {
+            uint32_t *fs = a.full_scores + (uint64_t)qi * a.n_docs;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                uint32_t m = valid[d];
+                while (m) {
+                    const int bit = __builtin_ctz(m);
+                    m &= m - 1;
+                    fs[a.order[sd.doc0 + lane * 128u + d * 32u + bit]] = cnt.score(d, bit);
+                }
+            }
+            continue;
+        }
+        if (qn.thr > qn.ell) continue;
+        uint32_t M[4];
+        cnt.ge(qn.thr, M);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) M[d] &= valid[d];
+        if (a.topk) {
+            const uint32_t have = wave_sum(__popc(M[0]) + __popc(M[1]) + __popc(M[2]) + __popc(M[3]));
+            if (have > a.topk) {
+                // MSB-first radix select of the topk-th largest score among M
+                uint32_t pre[4] = {M[0], M[1], M[2], M[3]};
+                uint32_t need = a.topk, s = 0;
+#pragma unroll
+                for (int p = P - 1; p >= 0; --p) {
+                    const uint32_t c1 = wave_sum(__popc(pre[0] & cnt.H[p][0]) + __popc(pre[1] & cnt.H[p][1]) +
+                                                 __popc(pre[2] & cnt.H[p][2]) + __popc(pre[3] & cnt.H[p][3]));
+                    if (c1 >= need) {
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) pre[d] &= cnt.H[p][d];
+                        s |= 1u << p;
+                    } else {
+                        need -= c1;
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) pre[d] &= ~cnt.H[p][d];
+                    }
+                }
+                uint32_t G[4];
+                cnt.ge(s, G);
+#pragma unroll
+                for (int d = 0; d < 4; ++d) M[d] &= G[d];
+            }
+        }
+        const uint32_t mine_n = __popc(M[0]) + __popc(M[1]) + __popc(M[2]) + __popc(M[3]);
+        const uint32_t tot = wave_sum(mine_n);
+        if (tot == 0) continue;
+        uint64_t base = 0;
+        if (lane == 0) {
+            base = atomicAdd(a.cand_counter, (unsigned long long)tot);
+            atomicAdd(&a.qcount[qi], tot);
+        }
+        base = bcast64(base);
+        uint64_t pos = base + wave_excl_scan(mine_n);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t m = M[d];
+            while (m) {
+                const int bit = __builtin_ctz(m);
+                m &= m - 1;
+                if (pos < a.cand_cap) {
+                    const uint32_t id = a.order[sd.doc0 + lane * 128u + d * 32u + bit];
+                    a.cand_key[pos] = ((uint64_t)cnt.score(d, bit) << 32) | (uint32_t)~id;
+                    a.cand_q[pos] = qi;
+                }
+                ++pos;
+            }
+        }
+    }
+}
+
+// ---- ordering of the hits ------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void group_scan_kernel(const uint32_t *qcount, uint32_t n,
+                                                          uint32_t topk, uint32_t *qstart,
+                                                          uint32_t *qcursor, uint32_t *out_start,
+                                                          uint32_t *out_n)
+{
+    __shared__ uint32_t s_a[1024], s_b[1024];
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t per = (n + nt - 1) / nt;
+    const uint32_t a = min(n, tid * per), b = min(n, a + per);
+    uint32_t sa = 0, sb = 0;
+    for (uint32_t q = a; q < b; ++q) {
+        const uint32_t c = qcount[q];
+        sa += c;
+        sb += topk ? min(c, topk) : c;
+    }
+    s_a[tid] = sa;
+    s_b[tid] = sb;
+    __syncthreads();
+    for (uint32_t o = 1; o < nt; o <<= 1) {
+        uint32_t x = 0, y = 0;
+        if (tid >= o) { x = s_a[tid - o]; y = s_b[tid - o]; }
+        __syncthreads();
+        s_a[tid] += x;
+        s_b[tid] += y;
+        __syncthreads();
+    }
+    uint32_t ra = s_a[tid] - sa, rb = s_b[tid] - sb;
+    for (uint32_t q = a; q < b; ++q) {
+        const uint32_t c = qcount[q];
+        const uint32_t k = topk ? min(c, topk) : c;
+        qstart[q] = ra;
+        qcursor[q] = 0;
+        out_start[q] = rb;
+        out_n[q] = k;
+        ra += c;
+        rb += k;
+    }
+    if (tid == nt - 1) { qstart[n] = s_a[nt - 1]; out_start[n] = s_b[nt - 1]; }
+}
+
+__global__ void group_scatter_kernel(const uint64_t *cand_key, const uint32_t *cand_q,
+                                     const unsigned long long *n_cand, uint64_t cap,
+                                     const uint32_t *qstart, uint32_t *qcursor, uint64_t *seg)
+{
+    const uint64_t n = *n_cand;
+    if (n > cap) return;   // overflow: the host enlarges the buffers and reruns
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t q = cand_q[i];
+        const uint32_t pos = qstart[q] + atomicAdd(&qcursor[q], 1u);
+        seg[pos] = cand_key[i];
+    }
+}
+
+// number of keys in the descending run b[0..n) that are greater than v
+__device__ __forceinline__ uint32_t count_greater(const uint64_t *b, uint32_t n, uint64_t v)
+{
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (b[mid] > v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// one workgroup per query: bitonic sort of runs of kSortRun keys in LDS, then
+// merge passes (every key finds its place by binary search; keys are distinct)
+__global__ __launch_bounds__(1024) void segsort_kernel(uint64_t *seg_a, uint64_t *seg_b,
+                                                       const unsigned long long *n_cand,
+                                                       uint64_t cap, const uint32_t *qstart,
+                                                       const uint32_t *out_start,
+                                                       const uint32_t *out_n, uint32_t *out_id,
+                                                       uint32_t *out_score)
+{
+    __shared__ uint64_t s[kSortRun];
+    if (*n_cand > cap) return;
+    const uint32_t q = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t beg = qstart[q], n = qstart[q + 1] - beg;
+    if (n == 0) return;
+    uint64_t *src = seg_a + beg, *dst = seg_b + beg;
+    for (uint32_t r0 = 0; r0 < n; r0 += kSortRun) {
+        const uint32_t rn = min(kSortRun, n - r0);
+        for (uint32_t i = tid; i < kSortRun; i += nt) s[i] = i < rn ? src[r0 + i] : 0ull;
+        __syncthreads();
+        for (uint32_t k = 2; k <= kSortRun; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = tid; i < kSortRun; i += nt) {
+                    const uint32_t ixj = i ^ j;
+                    if (ixj > i) {
+                        const uint64_t x = s[i], y = s[ixj];
+                        const bool desc = (i & k) == 0;
+                        if (desc ? (x < y) : (x > y)) { s[i] = y; s[ixj] = x; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = tid; i < rn; i += nt) src[r0 + i] = s[i];
+        __syncthreads();
+    }
+    for (uint32_t w = kSortRun; w < n; w <<= 1) {
+        for (uint32_t i = tid; i < n; i += nt) {
+            const uint32_t p0 = i / (2 * w) * (2 * w);
+            const uint32_t aN = min(w, n - p0);
+            const uint32_t bB = p0 + aN, bN = n > bB ? min(w, n - bB) : 0;
+            const uint64_t v = src[i];
+            uint32_t out;
+            if (i < bB) out = p0 + (i - p0) + count_greater(src + bB, bN, v);
+            else out = p0 + (i - bB) + count_greater(src + p0, aN, v);
+            dst[out] = v;
+        }
+        __syncthreads();
+        uint64_t *t = src; src = dst; dst = t;
+    }
+    const uint32_t o = out_start[q], k = out_n[q];
+    for (uint32_t i = tid; i < k; i += nt) {
+        const uint64_t v = src[i];
+        out_id[o + i] = ~(uint32_t)v;
+        out_score[o + i] = (uint32_t)(v >> 32);
+    }
+}
+
+// ---- construction --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void count_kernel(const uint8_t *bytes, const StrDesc *strs,
+                                                    uint32_t n_strs, uint64_t W,
+                                                    const uint64_t *tbase, const uint32_t *tlog2,
+                                                    uint64_t *table, uint32_t *empty_flag,
+                                                    unsigned long long *counts, TermSpec ts)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // wave-synchronous loop: every lane of a wave runs the same iterations
+    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < W; w0 += stride) {
+        const uint64_t w = w0 + lane;
+        bool uniq = false;
+        uint32_t d = 0;
+        if (w < W) {
+            uint32_t lo = 0, hi = n_strs;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (strs[mid].wbase <= w) lo = mid; else hi = mid;
+            }
+            const StrDesc sd = strs[lo];
+            d = sd.doc;
+            bool ok;
+            const uint64_t t = window_term(bytes + sd.byte_off + (w - sd.wbase), ts, ok);
+            if (ok) {
+                const uint64_t cap = 1ull << tlog2[d];
+                uniq = set_insert<false>(table + tbase[d], cap, t, mix64(t) & (cap - 1),
+                                         &empty_flag[d]);
+            }
+        }
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const bool same = __all((w >= W) || d == d0);
+        const unsigned long long m = __ballot(uniq);
+        if (same) {
+            if (lane == 0 && m) atomicAdd(&counts[d0], (unsigned long long)__popcll(m));
+        } else if (uniq) {
+            atomicAdd(&counts[d], 1ull);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void insert_kernel(const uint8_t *bytes, const StrDesc *strs,
+                                                     uint32_t n_strs, uint64_t W,
+                                                     const DocPos *pos, uint32_t *matrix,
+                                                     TermSpec ts, Seeds seeds)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < W; w += stride) {
+        uint32_t lo = 0, hi = n_strs;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (strs[mid].wbase <= w) lo = mid; else hi = mid;
+        }
+        const StrDesc sd = strs[lo];
+        bool ok;
+        const uint64_t t = window_term(bytes + sd.byte_off + (w - sd.wbase), ts, ok);
+        if (!ok) continue;
+        const DocPos p = pos[sd.doc];
+        const uint32_t bit = 1u << (p.col & 31u);
+        for (uint32_t i = 0; i < ts.h; ++i) {
+            const uint64_t row = mix64(t ^ seeds.s[i]) % p.rows;
+            atomicOr(matrix + (p.block_off + row * p.stride) / 4 + p.col / 32, bit);
+        }
+    }
+}
+
+__global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+}  // namespace
+
+uint64_t dedup_table_cap(uint64_t windows) { return table_cap(windows); }
+
+namespace {
+
+int grid_for(uint64_t n, int block)
+{
+    uint64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+template <int P>
+hipError_t launch_gather_p(const GatherArgs &a, int grid, hipStream_t st)
+{
+    if (a.h == 1)
+        hipLaunchKernelGGL((gather_kernel<P, true>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((gather_kernel<P, false>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const uint64_t *wbase,
+                          uint32_t n_queries, uint64_t W, TermSpec ts, uint64_t *terms,
+                          hipStream_t st)
+{
+    if (W == 0) return hipSuccess;
+    hipLaunchKernelGGL(extract_kernel, dim3(grid_for(W, 256)), dim3(256), 0, st, bytes, qstart,
+                       wbase, n_queries, W, ts, terms);
+    return hipGetLastError();
+}
+
+hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint64_t *tbase,
+                        uint64_t *table, uint64_t *uterms, uint64_t *hashes, uint32_t *nterms,
+                        uint32_t n_queries, TermSpec ts, Seeds seeds, hipStream_t st)
+{
+    if (n_queries == 0) return hipSuccess;
+    hipLaunchKernelGGL(dedup_kernel, dim3(n_queries), dim3(256), 0, st, terms, wbase, tbase,
+                       table, uterms, hashes, nterms, ts, seeds);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, uint32_t n_queries,
+                       uint32_t chunk, uint32_t n_slices, uint32_t k_num, uint32_t k_den,
+                       uint64_t ell_limit, QInfo *qinfo, uint32_t *chunk_prefix,
+                       uint64_t *total_items, unsigned long long *work_counter,
+                       unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, nterms, wbase, n_queries, chunk,
+                       n_slices, k_num, k_den, ell_limit, qinfo, chunk_prefix, total_items,
+                       work_counter, cand_counter, qcount, flags);
+    return hipGetLastError();
+}
+
+int gather_planes_for(uint64_t max_terms)
+{
+    int bits = 0;
+    while (bits < 64 && (max_terms >> bits) != 0) ++bits;
+    if (bits <= 8) return 8;
+    if (bits <= 12) return 12;
+    if (bits <= 16) return 16;
+    if (bits <= 20) return 20;
+    if (bits <= 24) return 24;
+    return 32;
+}
+
+hipError_t launch_gather(const GatherArgs &a, int planes, int grid, hipStream_t st)
+{
+    switch (planes) {
+    case 8: return launch_gather_p<8>(a, grid, st);
+    case 12: return launch_gather_p<12>(a, grid, st);
+    case 16: return launch_gather_p<16>(a, grid, st);
+    case 20: return launch_gather_p<20>(a, grid, st);
+    case 24: return launch_gather_p<24>(a, grid, st);
+    case 32: return launch_gather_p<32>(a, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int P, bool H1>
+static int occ_of()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, H1>, 256, 0) !=
+        hipSuccess)
+        blocks = 1;
+    return blocks < 1 ? 1 : blocks;
+}
+
+int gather_grid(int planes, int h)
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0) cus = 256;
+    }
+    int occ = 1;
+    const bool h1 = h == 1;
+    switch (planes) {
+    case 8: occ = h1 ? occ_of<8, true>() : occ_of<8, false>(); break;
+    case 12: occ = h1 ? occ_of<12, true>() : occ_of<12, false>(); break;
+    case 16: occ = h1 ? occ_of<16, true>() : occ_of<16, false>(); break;
+    case 20: occ = h1 ? occ_of<20, true>() : occ_of<20, false>(); break;
+    case 24: occ = h1 ? occ_of<24, true>() : occ_of<24, false>(); break;
+    default: occ = h1 ? occ_of<32, true>() : occ_of<32, false>(); break;
+    }
+    return cus * occ;
+}
+
+hipError_t launch_group_sort(const uint64_t *cand_key, const uint32_t *cand_q,
+                             const unsigned long long *n_cand, uint64_t cap, uint32_t n_queries,
+                             uint32_t topk, const uint32_t *qcount, uint32_t *qstart,
+                             uint32_t *qcursor, uint64_t *seg_a, uint64_t *seg_b,
+                             uint32_t *out_start, uint32_t *out_n, uint32_t *out_id,
+                             uint32_t *out_score, hipStream_t st)
+{
+    hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, st, qcount, n_queries, topk,
+                       qstart, qcursor, out_start, out_n);
+    hipLaunchKernelGGL(group_scatter_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, st, cand_key,
+                       cand_q, n_cand, cap, qstart, qcursor, seg_a);
+    hipLaunchKernelGGL(segsort_kernel, dim3(n_queries), dim3(1024), 0, st, seg_a, seg_b, n_cand,
+                       cap, qstart, out_start, out_n, out_id, out_score);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const uint8_t *bytes, const StrDesc *strs, uint32_t n_strs, uint64_t W,
+                        const uint64_t *tbase, const uint32_t *tlog2, uint64_t *table,
+                        uint32_t *empty_flag, unsigned long long *counts, TermSpec ts,
+                        hipStream_t st)
+{
+    if (W == 0) return hipSuccess;
+    hipLaunchKernelGGL(count_kernel, dim3(grid_for(W, 256)), dim3(256), 0, st, bytes, strs, n_strs,
+                       W, tbase, tlog2, table, empty_flag, counts, ts);
+    return hipGetLastError();
+}
+
+hipError_t launch_insert(const uint8_t *bytes, const StrDesc *strs, uint32_t n_strs, uint64_t W,
+                         const DocPos *pos, uint32_t *matrix, TermSpec ts, Seeds seeds,
+                         hipStream_t st)
+{
+    if (W == 0) return hipSuccess;
+    hipLaunchKernelGGL(insert_kernel, dim3(grid_for(W, 256)), dim3(256), 0, st, bytes, strs, n_strs,
+                       W, pos, matrix, ts, seeds);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace cobs

@@ -1,0 +1,950 @@
+// COBS library: construction, resident index, query batches, C ABI.
+//
+// Construction follows sections 2.1-2.3 of the COBS paper: exact distinct
+// q-gram counts per document, documents sorted by (count, input id) and cut
+// into blocks of B (classic: one block in input order), per-block filter size
+// m_b = max(1, ceil(-n_b h / ln(1 - p^(1/h)))), rows padded to 128 bytes,
+// one atomic OR per (term, hash).  The query path is section 2.2: hash the
+// query's distinct terms, gather and AND the h rows per term, ADD into
+// per-document scores, keep score >= ceil(K l) or the top-k.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <ctime>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+
+namespace cobs {
+
+static thread_local std::string g_err;
+
+cobs_status set_error(cobs_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+cobs_status hip_error(hipError_t e, const char *what)
+{
+    const cobs_status st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+                               ? COBS_ENOMEM : COBS_EDEVICE;
+    (void)hipGetLastError();
+    return set_error(st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+uint64_t now_ns()
+{
+    timespec t;
+    clock_gettime(CLOCK_MONOTONIC, &t);
+    return (uint64_t)t.tv_sec * 1000000000ull + (uint64_t)t.tv_nsec;
+}
+
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+hipError_t DevBuf::ensure(size_t bytes, bool zero, hipStream_t st)
+{
+    if (bytes <= cap && p) return hipSuccess;
+    release();
+    size_t want = bytes < 256 ? 256 : bytes + bytes / 4;
+    want = (want + 255) & ~size_t(255);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    cap = want;
+    if (zero) return hipMemsetAsync(p, 0, want, st);
+    return hipSuccess;
+}
+
+void HostBuf::release()
+{
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+hipError_t HostBuf::ensure(size_t bytes)
+{
+    if (bytes <= cap && p) return hipSuccess;
+    release();
+    size_t want = bytes < 4096 ? 4096 : bytes + bytes / 4;
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    cap = want;
+    return hipSuccess;
+}
+
+Workspace::~Workspace()
+{
+    for (hipEvent_t &e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+// process-wide gather timing (cobs_profile)
+static std::atomic<int> g_prof{0};
+static std::mutex g_prof_mu;
+static cobs_kernel_timing g_prof_acc{};
+
+static cobs_status check_params(const cobs_params *p)
+{
+    if (!p) return set_error(COBS_EINVAL, "params is NULL");
+    if (p->kind == COBS_TERMS_DNA) {
+        if (p->q < 1 || p->q > 31) return set_error(COBS_EINVAL, "DNA q must be in 1..31");
+    } else if (p->kind == COBS_TERMS_BYTES) {
+        if (p->q < 1 || p->q > 8) return set_error(COBS_EINVAL, "BYTES q must be in 1..8");
+    } else {
+        return set_error(COBS_EINVAL, "unknown term kind");
+    }
+    if (p->num_hashes < 1 || p->num_hashes > (uint32_t)kMaxHashes)
+        return set_error(COBS_EINVAL, "num_hashes must be in 1..8");
+    if (!(p->fpr > 0.0 && p->fpr < 1.0)) return set_error(COBS_EINVAL, "fpr must be in (0,1)");
+    return COBS_OK;
+}
+
+static Seeds make_seeds(uint64_t seed)
+{
+    // SplitMix64 (Steele, Lea, Flood 2014): seed_i is its i-th output
+    Seeds s{};
+    uint64_t st = seed;
+    for (int i = 0; i < kMaxHashes; ++i) {
+        st += 0x9E3779B97F4A7C15ull;
+        uint64_t z = st;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        s.s[i] = z ^ (z >> 31);
+    }
+    return s;
+}
+
+static TermSpec term_spec(const cobs_params &p)
+{
+    TermSpec t;
+    t.kind = p.kind;
+    t.q = p.q;
+    t.canonical = p.kind == COBS_TERMS_DNA ? (p.canonical ? 1u : 0u) : 0u;
+    t.h = p.num_hashes;
+    return t;
+}
+
+// Bloom filter rows for n distinct terms: the fixed-h inversion of the
+// false-positive rate (1 - e^(-hn/m))^h = p (section 2.1)
+static uint64_t filter_rows(uint64_t n, uint32_t h, double p)
+{
+    const double m = std::ceil(-(double)n * (double)h / std::log(1.0 - std::pow(p, 1.0 / (double)h)));
+    if (!(m >= 1.0)) return 1;
+    return (uint64_t)m;
+}
+
+}  // namespace cobs
+
+using namespace cobs;
+
+cobs_index::~cobs_index()
+{
+    for (Workspace *w : pool) delete w;
+    if (d_matrix) (void)hipFree(d_matrix);
+    if (d_order) (void)hipFree(d_order);
+    if (d_slices) (void)hipFree(d_slices);
+}
+
+// ---- construction -------------------------------------------------------------
+
+struct cobs_builder {
+    cobs_params prm{};
+    uint32_t n_docs = 0;
+    hipStream_t st = nullptr;
+    int device = 0;
+    int state = 0;   // 0 counting, 1 planned (inserting), 2 finished
+    std::vector<uint64_t> n_terms;
+    std::vector<uint8_t> counted, inserted;
+    std::vector<uint32_t> rank;   // input id -> sorted position
+    cobs_index *ix = nullptr;
+    DevBuf bytes, strs, tbase, tlog2, table, eflag, counts, pos;
+    ~cobs_builder() { delete ix; }
+};
+
+namespace {
+
+constexpr uint64_t kPieceWindows = 1ull << 27;
+
+struct Piece {
+    uint32_t d0, d1;   // documents of the run
+};
+
+cobs_status check_run(const cobs_builder *b, const cobs_docs *run, uint32_t first)
+{
+    if (!run) return set_error(COBS_EINVAL, "docs is NULL");
+    if ((uint64_t)first + run->n_docs > b->n_docs)
+        return set_error(COBS_EINVAL, "run exceeds the collection");
+    if (run->mem != COBS_MEM_HOST && run->mem != COBS_MEM_DEVICE)
+        return set_error(COBS_EINVAL, "docs.mem must be COBS_MEM_HOST or COBS_MEM_DEVICE");
+    if (run->n_docs == 0) return COBS_OK;
+    if (!run->str_off || !run->doc_str) return set_error(COBS_EINVAL, "docs offsets are NULL");
+    const uint64_t ns = run->doc_str[run->n_docs];
+    for (uint32_t d = 0; d < run->n_docs; ++d)
+        if (run->doc_str[d + 1] < run->doc_str[d])
+            return set_error(COBS_EINVAL, "doc_str must be non-decreasing");
+    for (uint64_t s = run->doc_str[0]; s < ns; ++s)
+        if (run->str_off[s + 1] < run->str_off[s])
+            return set_error(COBS_EINVAL, "str_off must be non-decreasing");
+    if (run->str_off[ns] > run->str_off[run->doc_str[0]] && !run->bytes)
+        return set_error(COBS_EINVAL, "docs.bytes is NULL");
+    return COBS_OK;
+}
+
+uint64_t doc_windows(const cobs_docs *run, uint32_t d, uint32_t q)
+{
+    uint64_t w = 0;
+    for (uint64_t s = run->doc_str[d]; s < run->doc_str[d + 1]; ++s) {
+        const uint64_t len = run->str_off[s + 1] - run->str_off[s];
+        if (len >= q) w += len - q + 1;
+    }
+    return w;
+}
+
+std::vector<Piece> cut_pieces(const cobs_docs *run, uint32_t q)
+{
+    std::vector<Piece> out;
+    uint32_t d0 = 0;
+    uint64_t acc = 0;
+    for (uint32_t d = 0; d < run->n_docs; ++d) {
+        const uint64_t w = doc_windows(run, d, q);
+        if (d > d0 && acc + w > kPieceWindows) {
+            out.push_back({d0, d});
+            d0 = d;
+            acc = 0;
+        }
+        acc += w;
+    }
+    if (d0 < run->n_docs) out.push_back({d0, run->n_docs});
+    return out;
+}
+
+// Device bytes and string table of one piece; returns windows in *W.
+cobs_status stage_piece(cobs_builder *b, const cobs_docs *run, const Piece &pc, uint64_t *W,
+                        const uint8_t **dbytes, uint32_t *n_strs)
+{
+    const uint32_t q = b->prm.q;
+    const uint64_t s0 = run->doc_str[pc.d0], s1 = run->doc_str[pc.d1];
+    const uint64_t byte0 = run->str_off[s0], byte1 = run->str_off[s1];
+    std::vector<StrDesc> strs;
+    strs.reserve(s1 - s0 + 1);
+    uint64_t w = 0;
+    for (uint32_t d = pc.d0; d < pc.d1; ++d) {
+        for (uint64_t s = run->doc_str[d]; s < run->doc_str[d + 1]; ++s) {
+            const uint64_t len = run->str_off[s + 1] - run->str_off[s];
+            const uint64_t nw = len >= q ? len - q + 1 : 0;
+            if (!nw) continue;
+            StrDesc sd{};
+            sd.byte_off = run->mem == COBS_MEM_HOST ? run->str_off[s] - byte0 : run->str_off[s];
+            sd.wbase = w;
+            sd.doc = d - pc.d0;
+            strs.push_back(sd);
+            w += nw;
+        }
+    }
+    StrDesc sentinel{};
+    sentinel.wbase = w;
+    strs.push_back(sentinel);
+    *W = w;
+    *n_strs = (uint32_t)strs.size() - 1;
+    COBS_HIP(b->strs.ensure(strs.size() * sizeof(StrDesc)));
+    COBS_HIP(hipMemcpyAsync(b->strs.p, strs.data(), strs.size() * sizeof(StrDesc),
+                            hipMemcpyHostToDevice, b->st));
+    if (run->mem == COBS_MEM_HOST) {
+        COBS_HIP(b->bytes.ensure(byte1 - byte0 + 64));
+        if (byte1 > byte0)
+            COBS_HIP(hipMemcpyAsync(b->bytes.p, run->bytes + byte0, byte1 - byte0,
+                                    hipMemcpyHostToDevice, b->st));
+        *dbytes = b->bytes.as<uint8_t>();
+    } else {
+        *dbytes = run->bytes;
+    }
+    return COBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cobs_last_error(void) { return g_err.c_str(); }
+
+uint64_t cobs_now_ns(void) { return now_ns(); }
+
+cobs_status cobs_builder_create(const cobs_params *params, uint32_t n_docs, void *stream,
+                                cobs_builder **out)
+{
+    if (!out) return set_error(COBS_EINVAL, "out is NULL");
+    *out = nullptr;
+    cobs_status s = check_params(params);
+    if (s != COBS_OK) return s;
+    auto *b = new cobs_builder();
+    b->prm = *params;
+    if (b->prm.kind != COBS_TERMS_DNA) b->prm.canonical = 0;
+    b->n_docs = n_docs;
+    b->st = (hipStream_t)stream;
+    (void)hipGetDevice(&b->device);
+    b->n_terms.assign(n_docs, 0);
+    b->counted.assign(n_docs, 0);
+    b->inserted.assign(n_docs, 0);
+    *out = b;
+    return COBS_OK;
+}
+
+void cobs_builder_free(cobs_builder *b) { delete b; }
+
+cobs_status cobs_builder_count(cobs_builder *b, const cobs_docs *run, uint32_t first)
+{
+    if (!b) return set_error(COBS_EINVAL, "builder is NULL");
+    if (b->state != 0) return set_error(COBS_ESTATE, "count after plan");
+    cobs_status s = check_run(b, run, first);
+    if (s != COBS_OK) return s;
+    const TermSpec ts = term_spec(b->prm);
+    for (const Piece &pc : cut_pieces(run, b->prm.q)) {
+        uint64_t W;
+        const uint8_t *dbytes;
+        uint32_t n_strs;
+        s = stage_piece(b, run, pc, &W, &dbytes, &n_strs);
+        if (s != COBS_OK) return s;
+        const uint32_t nd = pc.d1 - pc.d0;
+        std::vector<uint64_t> tb(nd);
+        std::vector<uint32_t> tl(nd);
+        uint64_t slots = 0;
+        for (uint32_t i = 0; i < nd; ++i) {
+            const uint64_t cap = dedup_table_cap(doc_windows(run, pc.d0 + i, b->prm.q));
+            uint32_t lg = 0;
+            while ((1ull << lg) < cap) ++lg;
+            tb[i] = slots;
+            tl[i] = lg;
+            slots += cap;
+        }
+        COBS_HIP(b->tbase.ensure(nd * 8));
+        COBS_HIP(b->tlog2.ensure(nd * 4));
+        COBS_HIP(b->table.ensure(slots * 8));
+        COBS_HIP(b->eflag.ensure(nd * 4));
+        COBS_HIP(b->counts.ensure(nd * 8));
+        COBS_HIP(hipMemcpyAsync(b->tbase.p, tb.data(), nd * 8, hipMemcpyHostToDevice, b->st));
+        COBS_HIP(hipMemcpyAsync(b->tlog2.p, tl.data(), nd * 4, hipMemcpyHostToDevice, b->st));
+        COBS_HIP(launch_fill_u64(b->table.as<uint64_t>(), slots, ~0ull, b->st));
+        COBS_HIP(hipMemsetAsync(b->eflag.p, 0, nd * 4, b->st));
+        COBS_HIP(hipMemsetAsync(b->counts.p, 0, nd * 8, b->st));
+        COBS_HIP(launch_count(dbytes, b->strs.as<StrDesc>(), n_strs, W, b->tbase.as<uint64_t>(),
+                              b->tlog2.as<uint32_t>(), b->table.as<uint64_t>(),
+                              b->eflag.as<uint32_t>(),
+                              b->counts.as<unsigned long long>(), ts, b->st));
+        std::vector<uint64_t> cnt(nd);
+        COBS_HIP(hipMemcpyAsync(cnt.data(), b->counts.p, nd * 8, hipMemcpyDeviceToHost, b->st));
+        COBS_HIP(hipStreamSynchronize(b->st));
+        for (uint32_t i = 0; i < nd; ++i) {
+            b->n_terms[first + pc.d0 + i] = cnt[i];
+            b->counted[first + pc.d0 + i] = 1;
+        }
+    }
+    return COBS_OK;
+}
+
+cobs_status cobs_builder_plan(cobs_builder *b)
+{
+    if (!b) return set_error(COBS_EINVAL, "builder is NULL");
+    if (b->state != 0) return set_error(COBS_ESTATE, "plan called twice");
+    for (uint32_t d = 0; d < b->n_docs; ++d)
+        if (!b->counted[d]) return set_error(COBS_ESTATE, "document " + std::to_string(d) + " not counted");
+    auto *ix = new cobs_index();
+    ix->prm = b->prm;
+    ix->device = b->device;
+    ix->n_docs = b->n_docs;
+    ix->n_terms = b->n_terms;
+    ix->seeds = make_seeds(b->prm.seed);
+    const uint32_t n = b->n_docs, B = b->prm.block_docs;
+    ix->order.resize(n);
+    std::iota(ix->order.begin(), ix->order.end(), 0u);
+    if (B) {
+        // compact: sort by (distinct terms, input id) -- sections 2.2, 2.3
+        std::stable_sort(ix->order.begin(), ix->order.end(), [&](uint32_t x, uint32_t y) {
+            return ix->n_terms[x] < ix->n_terms[y];
+        });
+    }
+    const uint32_t nb = n == 0 ? 0 : (B ? (n + B - 1) / B : 1);
+    uint64_t off = 0;
+    for (uint32_t k = 0; k < nb; ++k) {
+        Block blk{};
+        blk.first = B ? k * B : 0;
+        blk.docs = B ? std::min(B, n - blk.first) : n;
+        for (uint32_t j = 0; j < blk.docs; ++j)
+            blk.nmax = std::max(blk.nmax, ix->n_terms[ix->order[blk.first + j]]);
+        blk.rows = filter_rows(blk.nmax, b->prm.num_hashes, b->prm.fpr);
+        if (blk.rows > 0xFFFFFFFFull) {
+            delete ix;
+            return set_error(COBS_EINVAL, "block filter exceeds 2^32-1 rows");
+        }
+        blk.stride = ((blk.docs + 7) / 8 + 127) / 128 * 128;
+        blk.offset = off;
+        off += blk.rows * blk.stride;
+        off = (off + 255) & ~uint64_t(255);
+        ix->blocks.push_back(blk);
+        for (uint64_t s0 = 0; s0 < blk.stride; s0 += kSliceBytes) {
+            SliceDesc sd{};
+            sd.base = blk.offset + s0;
+            sd.stride = (uint32_t)blk.stride;
+            sd.rows = (uint32_t)blk.rows;
+            sd.width = (uint32_t)std::min<uint64_t>(kSliceBytes, blk.stride - s0);
+            const uint64_t dfirst = s0 * 8;
+            sd.ndocs = (uint32_t)(dfirst < blk.docs ? std::min<uint64_t>(kSliceBytes * 8, blk.docs - dfirst) : 0);
+            sd.doc0 = blk.first + (uint32_t)dfirst;
+            sd.block = k;
+            ix->slices.push_back(sd);
+        }
+    }
+    ix->total_bytes = off;
+    b->ix = ix;
+    if (off) {
+        hipError_t e = hipMalloc(&ix->d_matrix, off);
+        if (e != hipSuccess) { ix->d_matrix = nullptr; return hip_error(e, "hipMalloc(matrix)"); }
+        COBS_HIP(hipMemsetAsync(ix->d_matrix, 0, off, b->st));
+    }
+    COBS_HIP(hipMalloc(&ix->d_order, std::max<size_t>(n, 1) * 4));
+    if (n) COBS_HIP(hipMemcpyAsync(ix->d_order, ix->order.data(), n * 4, hipMemcpyHostToDevice, b->st));
+    COBS_HIP(hipMalloc(&ix->d_slices, std::max<size_t>(ix->slices.size(), 1) * sizeof(SliceDesc)));
+    if (!ix->slices.empty())
+        COBS_HIP(hipMemcpyAsync(ix->d_slices, ix->slices.data(), ix->slices.size() * sizeof(SliceDesc),
+                                hipMemcpyHostToDevice, b->st));
+    b->rank.resize(n);
+    for (uint32_t p = 0; p < n; ++p) b->rank[ix->order[p]] = p;
+    COBS_HIP(hipStreamSynchronize(b->st));
+    b->state = 1;
+    return COBS_OK;
+}
+
+cobs_status cobs_builder_insert(cobs_builder *b, const cobs_docs *run, uint32_t first)
+{
+    if (!b) return set_error(COBS_EINVAL, "builder is NULL");
+    if (b->state != 1) return set_error(COBS_ESTATE, "insert before plan or after finish");
+    cobs_status s = check_run(b, run, first);
+    if (s != COBS_OK) return s;
+    cobs_index *ix = b->ix;
+    const TermSpec ts = term_spec(b->prm);
+    const uint32_t B = b->prm.block_docs;
+    for (const Piece &pc : cut_pieces(run, b->prm.q)) {
+        uint64_t W;
+        const uint8_t *dbytes;
+        uint32_t n_strs;
+        s = stage_piece(b, run, pc, &W, &dbytes, &n_strs);
+        if (s != COBS_OK) return s;
+        const uint32_t nd = pc.d1 - pc.d0;
+        std::vector<DocPos> pos(nd);
+        for (uint32_t i = 0; i < nd; ++i) {
+            const uint32_t id = first + pc.d0 + i;
+            const uint32_t p = b->rank[id];
+            const uint32_t k = B ? p / B : 0;
+            const Block &blk = ix->blocks[k];
+            pos[i].block_off = blk.offset;
+            pos[i].rows = (uint32_t)blk.rows;
+            pos[i].stride = (uint32_t)blk.stride;
+            pos[i].col = p - blk.first;
+        }
+        COBS_HIP(b->pos.ensure(nd * sizeof(DocPos)));
+        COBS_HIP(hipMemcpyAsync(b->pos.p, pos.data(), nd * sizeof(DocPos), hipMemcpyHostToDevice, b->st));
+        COBS_HIP(launch_insert(dbytes, b->strs.as<StrDesc>(), n_strs, W, b->pos.as<DocPos>(),
+                               (uint32_t *)ix->d_matrix, ts, ix->seeds, b->st));
+        COBS_HIP(hipStreamSynchronize(b->st));
+        for (uint32_t i = 0; i < nd; ++i) b->inserted[first + pc.d0 + i] = 1;
+    }
+    return COBS_OK;
+}
+
+cobs_status cobs_builder_finish(cobs_builder *b, cobs_index **out)
+{
+    if (!b || !out) return set_error(COBS_EINVAL, "NULL argument");
+    if (b->state != 1) return set_error(COBS_ESTATE, "finish before plan");
+    for (uint32_t d = 0; d < b->n_docs; ++d)
+        if (!b->inserted[d]) return set_error(COBS_ESTATE, "document " + std::to_string(d) + " not inserted");
+    COBS_HIP(hipStreamSynchronize(b->st));
+    *out = b->ix;
+    b->ix = nullptr;
+    b->state = 2;
+    return COBS_OK;
+}
+
+cobs_status cobs_build(const cobs_params *params, const cobs_docs *docs, void *stream,
+                       cobs_index **out)
+{
+    if (!docs || !out) return set_error(COBS_EINVAL, "NULL argument");
+    *out = nullptr;
+    cobs_builder *b = nullptr;
+    cobs_status s = cobs_builder_create(params, docs->n_docs, stream, &b);
+    if (s == COBS_OK) s = cobs_builder_count(b, docs, 0);
+    if (s == COBS_OK) s = cobs_builder_plan(b);
+    if (s == COBS_OK) s = cobs_builder_insert(b, docs, 0);
+    if (s == COBS_OK) s = cobs_builder_finish(b, out);
+    delete b;
+    return s;
+}
+
+void cobs_index_free(cobs_index *ix) { delete ix; }
+
+cobs_status cobs_index_info(const cobs_index *ix, cobs_index_info_t *info)
+{
+    if (!ix || !info) return set_error(COBS_EINVAL, "NULL argument");
+    info->n_docs = ix->n_docs;
+    info->n_blocks = (uint32_t)ix->blocks.size();
+    info->params = ix->prm;
+    info->total_bytes = ix->total_bytes;
+    return COBS_OK;
+}
+
+cobs_status cobs_index_block(const cobs_index *ix, uint32_t b, uint32_t *first, uint32_t *docs,
+                             uint64_t *rows, uint64_t *stride, uint64_t *offset)
+{
+    if (!ix) return set_error(COBS_EINVAL, "index is NULL");
+    if (b >= ix->blocks.size()) return set_error(COBS_EINVAL, "block out of range");
+    const Block &k = ix->blocks[b];
+    if (first) *first = k.first;
+    if (docs) *docs = k.docs;
+    if (rows) *rows = k.rows;
+    if (stride) *stride = k.stride;
+    if (offset) *offset = k.offset;
+    return COBS_OK;
+}
+
+cobs_status cobs_index_order(const cobs_index *ix, uint32_t *order, uint64_t *n_terms)
+{
+    if (!ix) return set_error(COBS_EINVAL, "index is NULL");
+    if (order) std::memcpy(order, ix->order.data(), ix->order.size() * 4);
+    if (n_terms) std::memcpy(n_terms, ix->n_terms.data(), ix->n_terms.size() * 8);
+    return COBS_OK;
+}
+
+cobs_status cobs_index_read(const cobs_index *ix, uint64_t offset, uint64_t nbytes, void *dst)
+{
+    if (!ix || (!dst && nbytes)) return set_error(COBS_EINVAL, "NULL argument");
+    if (offset > ix->total_bytes || nbytes > ix->total_bytes - offset)
+        return set_error(COBS_EINVAL, "range outside the matrix");
+    if (nbytes) COBS_HIP(hipMemcpy(dst, ix->d_matrix + offset, nbytes, hipMemcpyDeviceToHost));
+    return COBS_OK;
+}
+
+}  // extern "C"
+
+// ---- query batches -------------------------------------------------------------------
+
+namespace cobs {
+
+Workspace *acquire_workspace(cobs_index *ix)
+{
+    std::lock_guard<std::mutex> g(ix->pool_mu);
+    if (!ix->pool.empty()) {
+        Workspace *w = ix->pool.back();
+        ix->pool.pop_back();
+        return w;
+    }
+    return new Workspace();
+}
+
+void release_workspace(cobs_index *ix, Workspace *ws)
+{
+    std::lock_guard<std::mutex> g(ix->pool_mu);
+    ix->pool.push_back(ws);
+}
+
+namespace {
+
+struct Scalars {
+    uint64_t total_items;
+    unsigned long long work_counter;
+    unsigned long long cand_counter;
+    uint32_t flags;
+    uint32_t pad;
+};
+
+uint32_t auto_chunk(uint64_t W, uint32_t n, uint32_t n_slices, int grid)
+{
+    // enough work items to fill the persistent grid twice, chunks of <= 1024
+    // terms so that one long query does not leave a tail
+    const uint64_t waves = (uint64_t)grid * 4;
+    const uint64_t base = (uint64_t)n * n_slices;
+    uint64_t c = 1024;
+    if (base < 2 * waves) {
+        const uint64_t want = 2 * waves - base;
+        c = (W * n_slices + want - 1) / want;
+    }
+    if (c < 32) c = 32;
+    if (c > 1024) c = 1024;
+    return (uint32_t)c;
+}
+
+}  // namespace
+
+cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStream_t st,
+                      BatchOut &out)
+{
+    const uint32_t n = b.n;
+    out.num_terms.assign(n, 0);
+    out.n.assign(n, 0);
+    out.start.assign(n + 1, 0);
+    if (n == 0) return COBS_OK;
+    if (!b.q_off) return set_error(COBS_EINVAL, "q_off is NULL");
+    if (b.k_den == 0) return set_error(COBS_EINVAL, "k_den must be > 0");
+    if (b.score_bits != 16 && b.score_bits != 32)
+        return set_error(COBS_EINVAL, "score_bits must be 16 or 32");
+    if (b.mem != COBS_MEM_HOST && b.mem != COBS_MEM_DEVICE)
+        return set_error(COBS_EINVAL, "mem must be COBS_MEM_HOST or COBS_MEM_DEVICE");
+    const uint32_t q = ix->prm.q, h = ix->prm.num_hashes;
+    const uint32_t n_slices = (uint32_t)ix->slices.size();
+    const uint64_t byte0 = b.mem == COBS_MEM_HOST ? b.q_off[0] : 0;
+    const uint64_t nbytes = b.q_off[n] - b.q_off[0];
+    if (nbytes && !b.bytes) return set_error(COBS_EINVAL, "bytes is NULL");
+
+    // host plan: windows, tables, partial-slot bound
+    std::vector<uint64_t> hv(2 * (size_t)n + 1);
+    uint64_t *qstart = hv.data(), *wbase = hv.data() + n;
+    uint64_t W = 0, maxw = 0, tslots = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (b.q_off[i + 1] < b.q_off[i]) return set_error(COBS_EINVAL, "q_off must be non-decreasing");
+        const uint64_t len = b.q_off[i + 1] - b.q_off[i];
+        const uint64_t nw = len >= q ? len - q + 1 : 0;
+        qstart[i] = b.q_off[i] - byte0;
+        wbase[i] = W;
+        W += nw;
+        maxw = std::max(maxw, nw);
+    }
+    wbase[n] = W;
+    std::vector<uint64_t> tb(n, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t cap = dedup_table_cap(wbase[i + 1] - wbase[i]);
+        if (cap > kLdsTableSlots) { tb[i] = tslots; tslots += cap; }
+    }
+    const int planes = gather_planes_for(maxw);
+    const int grid = gather_grid(planes, (int)h);
+    const uint32_t C = b.chunk ? b.chunk : auto_chunk(W, n, n_slices, grid);
+    uint64_t pslots = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t nw = wbase[i + 1] - wbase[i];
+        if (nw > C) pslots += (nw + C - 1) / C;
+    }
+    const TermSpec ts = term_spec(ix->prm);
+
+    // uploads
+    const size_t meta = (size_t)(2 * n + 1) * 8 + (size_t)n * 8;
+    COBS_HIP(ws.h_stage.ensure(meta + (b.mem == COBS_MEM_HOST ? nbytes : 0)));
+    uint8_t *stg = ws.h_stage.as<uint8_t>();
+    std::memcpy(stg, qstart, (size_t)n * 8);
+    std::memcpy(stg + (size_t)n * 8, wbase, (size_t)(n + 1) * 8);
+    std::memcpy(stg + (size_t)(2 * n + 1) * 8, tb.data(), (size_t)n * 8);
+    COBS_HIP(ws.qstart.ensure((size_t)n * 8));
+    COBS_HIP(ws.wbase.ensure((size_t)(n + 1) * 8));
+    COBS_HIP(ws.tbase.ensure((size_t)n * 8));
+    COBS_HIP(hipMemcpyAsync(ws.qstart.p, stg, (size_t)n * 8, hipMemcpyHostToDevice, st));
+    COBS_HIP(hipMemcpyAsync(ws.wbase.p, stg + (size_t)n * 8, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, st));
+    COBS_HIP(hipMemcpyAsync(ws.tbase.p, stg + (size_t)(2 * n + 1) * 8, (size_t)n * 8, hipMemcpyHostToDevice, st));
+    const uint8_t *dbytes = b.bytes;
+    if (b.mem == COBS_MEM_HOST) {
+        COBS_HIP(ws.bytes.ensure(nbytes + 64));
+        if (nbytes) {
+            std::memcpy(stg + meta, b.bytes + byte0, nbytes);
+            COBS_HIP(hipMemcpyAsync(ws.bytes.p, stg + meta, nbytes, hipMemcpyHostToDevice, st));
+        }
+        dbytes = ws.bytes.as<uint8_t>();
+    }
+
+    // a1-a3
+    COBS_HIP(ws.terms.ensure(std::max<uint64_t>(W, 1) * 8));
+    COBS_HIP(ws.uterms.ensure(std::max<uint64_t>(W, 1) * 8));
+    COBS_HIP(ws.hashes.ensure(std::max<uint64_t>(W, 1) * 8 * h));
+    COBS_HIP(ws.nterms.ensure((size_t)n * 4));
+    COBS_HIP(ws.table.ensure(std::max<uint64_t>(tslots, 1) * 8));
+    COBS_HIP(launch_extract(dbytes, ws.qstart.as<uint64_t>(), ws.wbase.as<uint64_t>(), n, W, ts,
+                            ws.terms.as<uint64_t>(), st));
+    COBS_HIP(launch_dedup(ws.terms.as<uint64_t>(), ws.wbase.as<uint64_t>(), ws.tbase.as<uint64_t>(),
+                          ws.table.as<uint64_t>(), ws.uterms.as<uint64_t>(),
+                          ws.hashes.as<uint64_t>(), ws.nterms.as<uint32_t>(), n, ts, ix->seeds, st));
+    if (b.terms_out) {
+        std::vector<uint32_t> nt(n);
+        COBS_HIP(hipMemcpyAsync(nt.data(), ws.nterms.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+        if (W) COBS_HIP(hipMemcpyAsync(b.terms_out, ws.uterms.p, W * 8, hipMemcpyDeviceToHost, st));
+        COBS_HIP(hipStreamSynchronize(st));
+        out.num_terms = nt;
+        return COBS_OK;
+    }
+
+    // a4-a8
+    const uint64_t tslots_need = (uint64_t)n * n_slices;
+    if (ws.tickets_slots < tslots_need || !ws.tickets.p) {
+        COBS_HIP(ws.tickets.ensure(std::max<uint64_t>(tslots_need, 1) * 4, true, st));
+        ws.tickets_slots = ws.tickets.cap / 4;
+    }
+    COBS_HIP(ws.qinfo.ensure((size_t)n * sizeof(QInfo)));
+    COBS_HIP(ws.chunk_prefix.ensure((size_t)(n + 1) * 4));
+    COBS_HIP(ws.scalars.ensure(sizeof(Scalars)));
+    COBS_HIP(ws.partials.ensure(std::max<uint64_t>(pslots * n_slices * (uint64_t)planes * 1024, 256)));
+    COBS_HIP(ws.qcount.ensure((size_t)n * 4));
+    COBS_HIP(hipMemsetAsync(ws.scalars.p, 0, sizeof(Scalars), st));
+    const uint64_t ell_limit = b.score_bits == 16 ? 0xFFFFull : 0xFFFFFFFFull;
+    const bool full = b.full_scores != nullptr;
+    if (ws.cand_cap == 0) ws.cand_cap = std::max<uint64_t>(1 << 20, (uint64_t)n * 64);
+    Scalars *dsc = ws.scalars.as<Scalars>();
+
+    for (int attempt = 0;; ++attempt) {
+        COBS_HIP(ws.cand_key.ensure(ws.cand_cap * 8));
+        COBS_HIP(ws.cand_q.ensure(ws.cand_cap * 4));
+        COBS_HIP(launch_plan(ws.nterms.as<uint32_t>(), ws.wbase.as<uint64_t>(), n, C, n_slices,
+                             b.k_num, b.k_den, ell_limit, ws.qinfo.as<QInfo>(),
+                             ws.chunk_prefix.as<uint32_t>(), &dsc->total_items, &dsc->work_counter,
+                             &dsc->cand_counter, ws.qcount.as<uint32_t>(), &dsc->flags, st));
+        if (full) {
+            COBS_HIP(ws.full.ensure(std::max<uint64_t>((uint64_t)n * ix->n_docs, 1) * 4));
+            COBS_HIP(hipMemsetAsync(ws.full.p, 0, (uint64_t)n * ix->n_docs * 4, st));
+        }
+        GatherArgs ga{};
+        ga.matrix = ix->d_matrix;
+        ga.slices = ix->d_slices;
+        ga.order = ix->d_order;
+        ga.hashes = ws.hashes.as<uint64_t>();
+        ga.qinfo = ws.qinfo.as<QInfo>();
+        ga.chunk_prefix = ws.chunk_prefix.as<uint32_t>();
+        ga.total_items = &dsc->total_items;
+        ga.work_counter = &dsc->work_counter;
+        ga.tickets = ws.tickets.as<uint32_t>();
+        ga.partials = ws.partials.as<uint32_t>();
+        ga.cand_counter = &dsc->cand_counter;
+        ga.cand_key = ws.cand_key.as<uint64_t>();
+        ga.cand_q = ws.cand_q.as<uint32_t>();
+        ga.qcount = ws.qcount.as<uint32_t>();
+        ga.full_scores = full ? ws.full.as<uint32_t>() : nullptr;
+        ga.cand_cap = ws.cand_cap;
+        ga.n_queries = n;
+        ga.n_slices = n_slices;
+        ga.h = h;
+        ga.chunk = C;
+        ga.topk = b.topk;
+        ga.n_docs = ix->n_docs;
+        const bool prof = g_prof.load() != 0;
+        if (prof) {
+            for (hipEvent_t &e : ws.ev)
+                if (!e) COBS_HIP(hipEventCreate(&e));
+            COBS_HIP(hipEventRecord(ws.ev[0], st));
+        }
+        if (n_slices) COBS_HIP(launch_gather(ga, planes, grid, st));
+        if (prof) COBS_HIP(hipEventRecord(ws.ev[1], st));
+        auto account = [&](const uint32_t *nt) -> cobs_status {
+            if (!prof) return COBS_OK;
+            float ms = 0.f;
+            COBS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]));
+            uint64_t terms = 0, per_term = 0;
+            for (uint32_t i = 0; i < n; ++i) terms += nt[i];
+            for (const SliceDesc &sd : ix->slices) per_term += sd.width;
+            std::lock_guard<std::mutex> g(g_prof_mu);
+            g_prof_acc.launches += 1;
+            g_prof_acc.total_ms += ms;
+            g_prof_acc.last_ms = ms;
+            g_prof_acc.terms += terms;
+            g_prof_acc.row_bytes += terms * h * per_term;
+            return COBS_OK;
+        };
+        if (full) {
+            Scalars hs;
+            COBS_HIP(hipMemcpyAsync(&hs, dsc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+            COBS_HIP(hipMemcpyAsync(out.num_terms.data(), ws.nterms.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+            if (ix->n_docs)
+                COBS_HIP(hipMemcpyAsync(b.full_scores, ws.full.p, (uint64_t)n * ix->n_docs * 4,
+                                        hipMemcpyDeviceToHost, st));
+            COBS_HIP(hipStreamSynchronize(st));
+            if (hs.flags & 1u) return set_error(COBS_EOVERFLOW, "a query exceeds the score width");
+            return account(out.num_terms.data());
+        }
+        COBS_HIP(ws.gstart.ensure((size_t)(n + 1) * 4));
+        COBS_HIP(ws.gcursor.ensure((size_t)n * 4));
+        COBS_HIP(ws.seg_a.ensure(ws.cand_cap * 8));
+        COBS_HIP(ws.seg_b.ensure(ws.cand_cap * 8));
+        COBS_HIP(ws.out_start.ensure((size_t)(n + 1) * 4));
+        COBS_HIP(ws.out_n.ensure((size_t)n * 4));
+        COBS_HIP(ws.out_id.ensure(ws.cand_cap * 4));
+        COBS_HIP(ws.out_score.ensure(ws.cand_cap * 4));
+        COBS_HIP(launch_group_sort(ws.cand_key.as<uint64_t>(), ws.cand_q.as<uint32_t>(),
+                                   &dsc->cand_counter, ws.cand_cap, n, b.topk,
+                                   ws.qcount.as<uint32_t>(), ws.gstart.as<uint32_t>(),
+                                   ws.gcursor.as<uint32_t>(), ws.seg_a.as<uint64_t>(),
+                                   ws.seg_b.as<uint64_t>(), ws.out_start.as<uint32_t>(),
+                                   ws.out_n.as<uint32_t>(), ws.out_id.as<uint32_t>(),
+                                   ws.out_score.as<uint32_t>(), st));
+        const size_t small = sizeof(Scalars) + (size_t)n * 4 * 2 + (size_t)(n + 1) * 4;
+        COBS_HIP(ws.h_small.ensure(small));
+        uint8_t *hs = ws.h_small.as<uint8_t>();
+        COBS_HIP(hipMemcpyAsync(hs, dsc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        COBS_HIP(hipMemcpyAsync(hs + sizeof(Scalars), ws.nterms.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+        COBS_HIP(hipMemcpyAsync(hs + sizeof(Scalars) + (size_t)n * 4, ws.out_n.p, (size_t)n * 4,
+                                hipMemcpyDeviceToHost, st));
+        COBS_HIP(hipMemcpyAsync(hs + sizeof(Scalars) + (size_t)n * 8, ws.out_start.p,
+                                (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, st));
+        COBS_HIP(hipStreamSynchronize(st));
+        Scalars sc;
+        std::memcpy(&sc, hs, sizeof(Scalars));
+        {
+            cobs_status a = account((const uint32_t *)(hs + sizeof(Scalars)));
+            if (a != COBS_OK) return a;
+        }
+        if (sc.flags & 1u) return set_error(COBS_EOVERFLOW, "a query exceeds the score width");
+        if (sc.cand_counter > ws.cand_cap) {
+            if (attempt >= 2) return set_error(COBS_EDEVICE, "candidate buffer kept overflowing");
+            ws.cand_cap = sc.cand_counter + sc.cand_counter / 4 + 1024;
+            continue;
+        }
+        std::memcpy(out.num_terms.data(), hs + sizeof(Scalars), (size_t)n * 4);
+        std::memcpy(out.n.data(), hs + sizeof(Scalars) + (size_t)n * 4, (size_t)n * 4);
+        std::memcpy(out.start.data(), hs + sizeof(Scalars) + (size_t)n * 8, (size_t)(n + 1) * 4);
+        const uint64_t total = out.start[n];
+        COBS_HIP(ws.h_out.ensure(std::max<uint64_t>(total, 1) * 8));
+        uint32_t *ho = ws.h_out.as<uint32_t>();
+        if (total) {
+            COBS_HIP(hipMemcpyAsync(ho, ws.out_id.p, total * 4, hipMemcpyDeviceToHost, st));
+            COBS_HIP(hipMemcpyAsync(ho + total, ws.out_score.p, total * 4, hipMemcpyDeviceToHost, st));
+            COBS_HIP(hipStreamSynchronize(st));
+        }
+        out.ids = ho;
+        out.scores = ho + total;
+        return COBS_OK;
+    }
+}
+
+cobs_status make_hits(const BatchOut &o, uint32_t q0, uint32_t n, cobs_hits *dst)
+{
+    for (uint32_t i = 0; i < n; ++i) {
+        cobs_hits &h = dst[i];
+        const uint32_t k = o.n[q0 + i], s = o.start[q0 + i];
+        h.n = k;
+        h.num_terms = o.num_terms[q0 + i];
+        h.doc_id = (uint32_t *)std::malloc(std::max<size_t>(k, 1) * 4);
+        h.score = (uint32_t *)std::malloc(std::max<size_t>(k, 1) * 4);
+        if (!h.doc_id || !h.score) return set_error(COBS_ENOMEM, "out of host memory");
+        if (k) {
+            std::memcpy(h.doc_id, o.ids + s, (size_t)k * 4);
+            std::memcpy(h.score, o.scores + s, (size_t)k * 4);
+        }
+    }
+    return COBS_OK;
+}
+
+}  // namespace cobs
+
+extern "C" {
+
+void cobs_hits_free(cobs_hits *hits, uint32_t n)
+{
+    if (!hits) return;
+    for (uint32_t i = 0; i < n; ++i) {
+        std::free(hits[i].doc_id);
+        std::free(hits[i].score);
+    }
+    std::free(hits);
+}
+
+cobs_status cobs_query_batch(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
+                             uint32_t n_queries, const cobs_query_opts *opts, void *stream,
+                             cobs_hits **out)
+{
+    if (!ix || !opts || !out) return set_error(COBS_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (opts->mode != COBS_MODE_BATCHED && opts->mode != COBS_MODE_PLAIN)
+        return set_error(COBS_EINVAL, "unknown mode");
+    hipStream_t st = (hipStream_t)stream;
+    cobs_hits *hits = (cobs_hits *)std::calloc(std::max<uint32_t>(n_queries, 1), sizeof(cobs_hits));
+    if (!hits) return set_error(COBS_ENOMEM, "out of host memory");
+    Workspace *ws = acquire_workspace(ix);
+    BatchSpec spec;
+    spec.bytes = bytes;
+    spec.mem = opts->mem;
+    spec.k_num = opts->k_num;
+    spec.k_den = opts->k_den;
+    spec.topk = opts->topk;
+    spec.score_bits = opts->score_bits;
+    cobs_status s = COBS_OK;
+    BatchOut bo;
+    if (opts->mode == COBS_MODE_BATCHED) {
+        spec.q_off = q_off;
+        spec.n = n_queries;
+        s = run_batch(ix, *ws, spec, st, bo);
+        if (s == COBS_OK) s = make_hits(bo, 0, n_queries, hits);
+    } else {
+        // one query per launch of the pipeline
+        for (uint32_t i = 0; i < n_queries && s == COBS_OK; ++i) {
+            spec.q_off = q_off + i;
+            spec.n = 1;
+            s = run_batch(ix, *ws, spec, st, bo);
+            if (s == COBS_OK) s = make_hits(bo, 0, 1, hits + i);
+        }
+    }
+    release_workspace(ix, ws);
+    if (s != COBS_OK) {
+        cobs_hits_free(hits, n_queries);
+        return s;
+    }
+    *out = hits;
+    return COBS_OK;
+}
+
+cobs_status cobs_query_scores(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
+                              uint32_t n_queries, uint32_t mem, void *stream, uint32_t *scores,
+                              uint32_t *num_terms)
+{
+    if (!ix || (!scores && n_queries && ix->n_docs)) return set_error(COBS_EINVAL, "NULL argument");
+    Workspace *ws = acquire_workspace(ix);
+    BatchSpec spec;
+    spec.bytes = bytes;
+    spec.q_off = q_off;
+    spec.n = n_queries;
+    spec.mem = mem;
+    spec.full_scores = scores ? scores : (uint32_t *)&spec;
+    BatchOut bo;
+    cobs_status s = run_batch(ix, *ws, spec, (hipStream_t)stream, bo);
+    release_workspace(ix, ws);
+    if (s == COBS_OK && num_terms) std::memcpy(num_terms, bo.num_terms.data(), (size_t)n_queries * 4);
+    return s;
+}
+
+cobs_status cobs_query_terms(const cobs_index *cix, const uint8_t *bytes, const uint64_t *q_off,
+                             uint32_t n_queries, uint32_t mem, void *stream, uint64_t *terms,
+                             uint32_t *num_terms)
+{
+    cobs_index *ix = const_cast<cobs_index *>(cix);
+    if (!ix || !terms) return set_error(COBS_EINVAL, "NULL argument");
+    Workspace *ws = acquire_workspace(ix);
+    BatchSpec spec;
+    spec.bytes = bytes;
+    spec.q_off = q_off;
+    spec.n = n_queries;
+    spec.mem = mem;
+    spec.terms_out = terms;
+    BatchOut bo;
+    cobs_status s = run_batch(ix, *ws, spec, (hipStream_t)stream, bo);
+    release_workspace(ix, ws);
+    if (s == COBS_OK && num_terms) std::memcpy(num_terms, bo.num_terms.data(), (size_t)n_queries * 4);
+    return s;
+}
+
+cobs_status cobs_profile(int enable)
+{
+    g_prof.store(enable ? 1 : 0);
+    return COBS_OK;
+}
+
+cobs_status cobs_profile_read(cobs_kernel_timing *gather, int reset)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (gather) *gather = g_prof_acc;
+    if (reset) g_prof_acc = cobs_kernel_timing{};
+    return COBS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Host runtime of the COBS library: device buffers, the resident index and
+// the query-batch pipeline shared by cobs_query_batch and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cobs.h"
+#include "kernels.h"
+
+namespace cobs {
+
+cobs_status set_error(cobs_status st, const std::string &msg);
+cobs_status hip_error(hipError_t e, const char *what);
+
+#define COBS_HIP(call)                                            \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::cobs::hip_error(e_, #call); \
+    } while (0)
+
+// grow-only device buffer
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release();
+    hipError_t ensure(size_t bytes, bool zero = false, hipStream_t st = nullptr);
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+// grow-only pinned host buffer
+struct HostBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf() { release(); }
+    void release();
+    hipError_t ensure(size_t bytes);
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+struct Block {
+    uint32_t first, docs;
+    uint64_t rows, stride, offset, nmax;
+};
+
+// Everything one query batch needs on the device; reused across batches.
+struct Workspace {
+    DevBuf bytes, qstart, wbase, terms, uterms, hashes, nterms, table, tbase;
+    DevBuf tickets, qinfo, chunk_prefix, scalars, partials;
+    DevBuf cand_key, cand_q, qcount, gstart, gcursor, seg_a, seg_b;
+    DevBuf out_start, out_n, out_id, out_score, full;
+    HostBuf h_stage, h_small, h_out;
+    uint64_t tickets_slots = 0;
+    uint64_t cand_cap = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};   // gather timing (cobs_profile)
+    ~Workspace();
+};
+
+// Host view of a query batch's results.
+struct BatchOut {
+    std::vector<uint32_t> num_terms;   // l per query
+    std::vector<uint32_t> n;           // hits per query
+    std::vector<uint32_t> start;       // first hit per query
+    const uint32_t *ids = nullptr;     // pinned, valid until the next batch
+    const uint32_t *scores = nullptr;
+};
+
+struct BatchSpec {
+    const uint8_t *bytes = nullptr;
+    const uint64_t *q_off = nullptr;
+    uint32_t n = 0;
+    uint32_t mem = COBS_MEM_HOST;
+    uint32_t k_num = 0, k_den = 1, topk = 0, score_bits = 32;
+    uint32_t chunk = 0;                // 0 = automatic
+    uint32_t *full_scores = nullptr;   // host [n * n_docs]: full score mode
+    uint64_t *terms_out = nullptr;     // host [windows]: terms-only mode
+};
+
+}  // namespace cobs
+
+struct cobs_index {
+    cobs_params prm{};
+    int device = 0;
+    uint32_t n_docs = 0;
+    std::vector<cobs::Block> blocks;
+    std::vector<uint32_t> order;       // sorted position -> input id
+    std::vector<uint64_t> n_terms;     // per input id
+    std::vector<cobs::SliceDesc> slices;
+    uint8_t *d_matrix = nullptr;
+    uint64_t total_bytes = 0;
+    uint32_t *d_order = nullptr;
+    cobs::SliceDesc *d_slices = nullptr;
+    cobs::Seeds seeds{};
+    std::mutex pool_mu;
+    std::vector<cobs::Workspace *> pool;
+    ~cobs_index();
+};
+
+namespace cobs {
+
+Workspace *acquire_workspace(cobs_index *ix);
+void release_workspace(cobs_index *ix, Workspace *ws);
+
+// Run one query batch end to end on stream st (synchronises st).
+cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStream_t st,
+                      BatchOut &out);
+
+// Fill library-owned cobs_hits from a BatchOut (queries [q0, q0+n)).
+cobs_status make_hits(const BatchOut &o, uint32_t q0, uint32_t n, cobs_hits *dst);
+
+uint64_t now_ns();
+
+}  // namespace cobs

@@ -1,0 +1,153 @@
+"""CPU-side checks: the C ABI library loads and exports every declared entry
+point, the input generators behave as specified, the bench refuses more than
+one GPU.  No GPU calls."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1905_09624_amd", "libcobs.so")
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "cobs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cobs_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def built_lib():
+    if not os.path.exists(LIB):
+        from paper_1905_09624_amd import build
+        build.build()
+    return LIB
+
+
+def test_library_exports_every_declared_symbol(built_lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    L = ctypes.CDLL(built_lib)
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/cobs.h but not exported"
+    out = subprocess.check_output(["nm", "-D", "--defined-only", built_lib]).decode()
+    exported = set(re.findall(r" T (cobs_[a-z_0-9]+)", out))
+    assert set(names) <= exported
+
+
+def test_binding_covers_abi(built_lib):
+    import paper_1905_09624_amd as cobs
+    assert set(declared_functions()) == set(cobs.EXPORTS)
+    cobs.lib()
+
+
+def test_library_does_not_link_the_oracle(built_lib):
+    out = subprocess.check_output(["nm", "-D", built_lib]).decode()
+    assert "orc_" not in out
+    deps = subprocess.check_output(["ldd", built_lib]).decode()
+    assert "oracle" not in deps
+
+
+def test_product_sources_do_not_reference_oracle():
+    pkg = os.path.join(ROOT, "paper_1905_09624_amd")
+    for dp, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dp, f)).read()
+                assert "import oracle" not in text and "cobs_oracle" not in text, f
+
+
+# ---- generator ---------------------------------------------------------------
+
+def test_philox_known_answers():
+    # Random123 known-answer vectors for Philox4x32-10
+    assert synth.philox([0, 0, 0, 0], [0, 0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    assert synth.philox([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2) == [
+        0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]
+    assert synth.philox([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344],
+                        [0xA4093822, 0x299F31D0]) == [0xD16CFE09, 0x94FDCCEB, 0x5001E420,
+                                                      0x24126EA1]
+
+
+def test_doc_lengths_follow_recipes():
+    w1 = synth.CONFIGS[1]
+    l1 = synth.doc_lengths(w1)
+    assert l1.min() >= 10_000 and l1.max() <= 100_000
+    assert abs(l1.mean() - 55_000) < 3_000
+    w3 = synth.CONFIGS[3].scaled(100)
+    l3 = synth.doc_lengths(w3).astype(np.float64) - 30
+    med = np.median(l3)
+    assert 0.85 * 1e4 < med < 1.15 * 1e4
+    assert l3.max() <= 8e4
+    sig = np.std(np.log(np.maximum(l3[l3 < 8e4], 1)))
+    assert 0.6 < sig < 0.8
+
+
+def test_docs_are_deterministic_and_uniform():
+    w = synth.CONFIGS[1].scaled(100)
+    a = synth.dna_docs(w)
+    b = synth.dna_docs(w)
+    assert np.array_equal(a.bytes, b.bytes)
+    counts = np.bincount(a.bytes, minlength=256)
+    sd = (0.25 * 0.75 / a.bytes.size) ** 0.5
+    assert counts[[ord(c) for c in "ACGT"]].sum() == a.bytes.size
+    for c in b"ACGT":
+        assert abs(counts[c] / a.bytes.size - 0.25) < 4 * sd
+    # random access agrees with the bulk generator
+    for d in (0, 3):
+        off = int(a.str_off[d])
+        for i in (0, 1, 63, 64, 100):
+            assert synth.doc_base(w.seed, d, i) == a.bytes[off + i]
+
+
+def test_planted_queries_copy_their_source():
+    w = synth.CONFIGS[2].scaled(100)
+    d = synth.dna_docs(w)
+    qs = synth.dna_queries(w, n=40)
+    planted = [i for i in range(qs.n) if qs.src[i] >= 0]
+    assert len(planted) == 20
+    total = diff = 0
+    for i in planted:
+        q = np.frombuffer(qs.get(i), np.uint8)
+        doc = d.bytes[int(d.str_off[qs.src[i]]):int(d.str_off[qs.src[i] + 1])].tobytes()
+        # find the offset by matching the longest exact prefix
+        best = None
+        for off in range(len(doc) - len(q) + 1):
+            mism = np.count_nonzero(np.frombuffer(doc[off:off + len(q)], np.uint8) != q)
+            if best is None or mism < best:
+                best = mism
+            if mism <= 0.05 * len(q):
+                break
+        total += len(q)
+        diff += best
+    assert 0.004 < diff / total < 0.02
+
+
+def test_text_generator_shapes():
+    w = synth.CONFIGS[4].scaled(1000)
+    d = synth.text_docs(w)
+    lens = np.diff(d.str_off.astype(np.int64))
+    assert lens.min() >= 1
+    assert np.count_nonzero(d.bytes == 0x20) > 0.05 * d.bytes.size
+    qs = synth.text_queries(w, d, n=10)
+    assert all(16 <= len(qs.get(i)) <= 4096 for i in range(qs.n))
+
+
+def test_arrivals_are_poisson():
+    t = synth.arrivals(7, 20000, 1000.0)
+    gaps = np.diff(t)
+    assert abs(gaps.mean() - 1e-3) < 5e-5
+    assert abs(gaps.std() - 1e-3) < 1e-4
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)

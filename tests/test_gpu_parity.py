@@ -1,0 +1,297 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element, on seeded inputs.  Integer results: bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _cobs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_09624_amd as cobs
+    return cobs
+
+
+def build_both(docs, kind, q, canonical, h, p, B, seed):
+    cobs = _cobs()
+    prm = cobs.make_params(kind, q, canonical, h, p, B, seed)
+    gix = cobs.Index.build(prm, docs.bytes, docs.str_off, docs.doc_str)
+    oix = oracle.OracleIndex(oracle.Docs(docs.bytes, docs.str_off, docs.doc_str), kind=kind, q=q,
+                             canonical=canonical, h=h, p=p, B=B, seed=seed)
+    return gix, oix
+
+
+def assert_same_index(gix, oix):
+    order, nterms = gix.order()
+    assert np.array_equal(nterms, oix.n_terms())
+    assert np.array_equal(order, oix.order())
+    assert gix.info()["n_blocks"] == oix.n_blocks
+    omat = oix.matrix()
+    for b in range(oix.n_blocks):
+        gb, ob = gix.block(b), oix.block(b)
+        for k in ("first", "docs", "rows", "stride"):
+            assert gb[k] == ob[k], (b, k)
+        n = ob["rows"] * ob["stride"]
+        assert np.array_equal(gix.read(gb["offset"], n), omat[ob["offset"]:ob["offset"] + n]), b
+
+
+def queries_of(strings):
+    data = b"".join(strings)
+    off = np.zeros(len(strings) + 1, np.uint64)
+    off[1:] = np.cumsum([len(s) for s in strings])
+    return np.frombuffer(data, np.uint8).copy() if data else np.zeros(0, np.uint8), off
+
+
+def rand_dna(rng, n, alphabet=b"ACGT"):
+    return bytes(rng.choice(np.frombuffer(alphabet, np.uint8), size=n))
+
+
+def check_queries(gix, oix, data, off, k=(4, 5), topk=0, mode=0):
+    res = gix.query(data, off, k=k, topk=topk, mode=mode)
+    for i in range(len(off) - 1):
+        qb = data[int(off[i]):int(off[i + 1])].tobytes()
+        ids, sc, l = oix.query(qb, k[0], k[1], topk)
+        gids, gsc, gl = res[i]
+        assert gl == l, (i, gl, l)
+        assert np.array_equal(gids, ids), (i, gids[:10], ids[:10])
+        assert np.array_equal(gsc, sc), i
+
+
+# ---- construction -----------------------------------------------------------
+
+@pytest.mark.parametrize("case", [
+    dict(kind=0, q=31, canonical=True, h=1, p=0.3, B=0),
+    dict(kind=0, q=31, canonical=True, h=1, p=0.3, B=8),
+    dict(kind=0, q=11, canonical=False, h=3, p=0.1, B=5),
+    dict(kind=1, q=8, canonical=False, h=3, p=0.1, B=16),
+    dict(kind=1, q=3, canonical=False, h=2, p=0.3, B=0),
+])
+def test_build_matrix_bitexact(case):
+    rng = np.random.default_rng(5)
+    docs = []
+    for i in range(37):
+        n = int(rng.integers(0, 3000))
+        if case["kind"] == 0:
+            alph = b"ACGTN" if i % 5 == 0 else b"acgtACGT"
+            docs.append([rand_dna(rng, n, alph), rand_dna(rng, n // 3)])
+        else:
+            docs.append([bytes(rng.integers(0, 256, n, dtype=np.uint8))])
+    d = oracle.Docs.from_lists(docs)
+    gix, oix = build_both(d, seed=99, **case)
+    assert_same_index(gix, oix)
+
+
+def test_build_wide_classic_block_multiple_slices():
+    # 9000 documents in one classic block: 1128-byte rows, two column slices
+    rng = np.random.default_rng(8)
+    d = oracle.Docs.from_lists([rand_dna(rng, int(rng.integers(31, 80))) for _ in range(9000)])
+    gix, oix = build_both(d, 0, 31, True, 1, 0.3, 0, 7)
+    assert_same_index(gix, oix)
+    data, off = queries_of([rand_dna(rng, 200) for _ in range(5)] +
+                           [d.bytes[int(d.str_off[j]):int(d.str_off[j + 1])].tobytes()
+                            for j in (0, 4000, 8999)])
+    sc, l = gix.scores(data, off)
+    for i in range(len(off) - 1):
+        want, wl = oix.query_scores(data[int(off[i]):int(off[i + 1])].tobytes())
+        assert wl == l[i]
+        assert np.array_equal(sc[i], want)
+    check_queries(gix, oix, data, off, k=(1, 2))
+
+
+def test_streamed_build_equals_one_call():
+    cobs = _cobs()
+    w = synth.CONFIGS[3].scaled(500)
+    d = synth.docs(w)
+    prm = cobs.make_params(0, w.q, w.canonical, w.h, w.p, w.B, w.hash_seed)
+    one = cobs.Index.build(prm, d.bytes, d.str_off, d.doc_str)
+    n = d.n_docs
+    cuts = [0, 17, 18, 90, n]
+
+    def runs(pass_no):
+        order = range(len(cuts) - 1) if pass_no == 0 else reversed(range(len(cuts) - 1))
+        for k in order:
+            a, b = cuts[k], cuts[k + 1]
+            sub = synth.dna_docs(w, first=a, count=b - a)
+            yield a, sub.bytes, sub.str_off, sub.doc_str
+
+    two = cobs.Index.build_streamed(prm, n, runs)
+    assert one.info() == two.info()
+    nb = one.info()["total_bytes"]
+    assert np.array_equal(one.read(0, nb), two.read(0, nb))
+
+
+# ---- query steps -----------------------------------------------------------------
+
+def test_terms_and_dedup_match_oracle():
+    cobs = _cobs()
+    rng = np.random.default_rng(2)
+    d = oracle.Docs.from_lists([rand_dna(rng, 500)])
+    prm = cobs.make_params(0, 31, True, 1, 0.3, 0, 1)
+    gix = cobs.Index.build(prm, d.bytes, d.str_off, d.doc_str)
+    qs = [b"", b"ACGT", rand_dna(rng, 31), rand_dna(rng, 5000, b"ACGTN"),
+          rand_dna(rng, 200) * 5, b"acgtNNACGTAC" * 40, rand_dna(rng, 20000)]
+    data, off = queries_of(qs)
+    got = gix.terms(data, off, q=31)
+    for i, s in enumerate(qs):
+        want = oracle.unique(oracle.terms(0, 31, True, s))
+        assert np.array_equal(np.sort(got[i]), want), i
+
+
+def test_bytes_terms_with_all_ones_term():
+    cobs = _cobs()
+    d = oracle.Docs.from_lists([b"\xff" * 40 + b"abcdefghij"])
+    prm = cobs.make_params(1, 8, False, 3, 0.1, 0, 3)
+    gix = cobs.Index.build(prm, d.bytes, d.str_off, d.doc_str)
+    qs = [b"\xff" * 20, b"\xff" * 9 + b"abc", b"xyz"]
+    data, off = queries_of(qs)
+    got = gix.terms(data, off, q=8)
+    for i, s in enumerate(qs):
+        assert np.array_equal(np.sort(got[i]), oracle.unique(oracle.terms(1, 8, False, s)))
+    assert gix.order()[1][0] == 3 + 8   # distinct 8-grams of the document
+
+
+# ---- scores and hits on scaled workloads -------------------------------------------
+
+WORKLOADS = {
+    "classic-1k/s4": (synth.CONFIGS[1].scaled(4), 40),
+    "classic-10k/s20": (synth.CONFIGS[2].scaled(20), 40),
+    "compact-100k/s100": (synth.CONFIGS[3].scaled(100), 40),
+    "text-50k/s50": (synth.CONFIGS[4].scaled(50), 60),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(WORKLOADS))
+def workload(request):
+    w, nq = WORKLOADS[request.param]
+    d = synth.docs(w)
+    qs = synth.dna_queries(w, n=nq) if w.kind == "dna" else synth.text_queries(w, d, n=nq)
+    kind = 0 if w.kind == "dna" else 1
+    gix, oix = build_both(d, kind, w.q, w.canonical, w.h, w.p, w.B, w.hash_seed)
+    return w, d, qs, gix, oix
+
+
+def test_workload_index_bitexact(workload):
+    w, d, qs, gix, oix = workload
+    assert_same_index(gix, oix)
+
+
+def test_workload_full_scores(workload):
+    w, d, qs, gix, oix = workload
+    sc, l = gix.scores(qs.bytes, qs.q_off)
+    for i in range(qs.n):
+        want, wl = oix.query_scores(qs.get(i))
+        assert l[i] == wl
+        assert np.array_equal(sc[i], want), i
+
+
+@pytest.mark.parametrize("k,topk", [((4, 5), 0), ((0, 1), 10), ((1, 2), 3), ((0, 1), 0)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_workload_hits(workload, k, topk, mode):
+    w, d, qs, gix, oix = workload
+    check_queries(gix, oix, qs.bytes, qs.q_off, k=k, topk=topk, mode=mode)
+
+
+def test_planted_source_never_missed(workload):
+    # no false negatives: the source document scores at least the exact overlap
+    w, d, qs, gix, oix = workload
+    sc, l = gix.scores(qs.bytes, qs.q_off)
+    kind = 0 if w.kind == "dna" else 1
+    all_docs = oracle.Docs(d.bytes, d.str_off, d.doc_str)
+    for i in range(qs.n):
+        if qs.src[i] < 0:
+            continue
+        s = int(qs.src[i])
+        ex, _ = oracle.exact_intersection(all_docs, qs.get(i), kind=kind, q=w.q,
+                                          canonical=w.canonical)
+        assert sc[i][s] >= ex[s]
+        assert np.all(sc[i] >= ex)
+
+
+# ---- edge cases -----------------------------------------------------------------
+
+def test_edge_queries():
+    rng = np.random.default_rng(4)
+    docs = oracle.Docs.from_lists([rand_dna(rng, int(rng.integers(100, 4000))) for _ in range(25)]
+                                  + [b"", b"ACG", b"N" * 100])
+    gix, oix = build_both(docs, 0, 31, True, 1, 0.3, 6, 11)
+    assert_same_index(gix, oix)
+    src = docs.bytes[int(docs.str_off[3]):int(docs.str_off[4])].tobytes()
+    qs = [b"", b"A" * 30, b"N" * 64, src, src[:31], src * 3, rand_dna(rng, 9000),
+          src[:500] + b"N" + src[500:], b"ACGT" * 2000]
+    data, off = queries_of(qs)
+    for k, topk in (((4, 5), 0), ((0, 1), 5), ((1, 1), 0), ((3, 2), 0)):
+        check_queries(gix, oix, data, off, k=k, topk=topk, mode=0)
+        check_queries(gix, oix, data, off, k=k, topk=topk, mode=1)
+    assert gix.query(data[:0], np.zeros(1, np.uint64)) == []
+
+
+def test_long_query_multi_chunk_and_global_table():
+    # > 4096 windows: dedup table in global memory; > 1024 terms: several
+    # chunks merged by the last wavefront of each (query, slice)
+    rng = np.random.default_rng(6)
+    docs = oracle.Docs.from_lists([rand_dna(rng, 30000) for _ in range(12)])
+    gix, oix = build_both(docs, 0, 31, True, 1, 0.3, 4, 2)
+    d0 = docs.bytes[int(docs.str_off[0]):int(docs.str_off[1])].tobytes()
+    qs = [d0[:20000] + rand_dna(rng, 30000), rand_dna(rng, 70000), d0]
+    data, off = queries_of(qs)
+    sc, l = gix.scores(data, off)
+    for i, s in enumerate(qs):
+        want, wl = oix.query_scores(s)
+        assert l[i] == wl
+        assert np.array_equal(sc[i], want)
+    check_queries(gix, oix, data, off, k=(1, 5), topk=0, mode=0)
+    check_queries(gix, oix, data, off, k=(0, 1), topk=7, mode=1)
+
+
+def test_score_width_overflow():
+    cobs = _cobs()
+    rng = np.random.default_rng(9)
+    docs = oracle.Docs.from_lists([rand_dna(rng, 200)])
+    prm = cobs.make_params(0, 31, True, 1, 0.3, 0, 1)
+    gix = cobs.Index.build(prm, docs.bytes, docs.str_off, docs.doc_str)
+    data, off = queries_of([rand_dna(rng, 70000)])
+    with pytest.raises(cobs.CobsError) as e:
+        gix.query(data, off, score_bits=16)
+    assert e.value.status == cobs.EOVERFLOW
+    gix.query(data, off, score_bits=32)
+
+
+def test_invalid_arguments():
+    cobs = _cobs()
+    docs = oracle.Docs.from_lists([b"ACGT" * 20])
+    for bad in (dict(q=32), dict(q=0), dict(h=0), dict(h=9), dict(p=0.0), dict(p=1.0)):
+        kw = dict(kind=0, q=31, canonical=True, h=1, p=0.3, B=0, seed=1)
+        kw.update(bad)
+        with pytest.raises(cobs.CobsError) as e:
+            cobs.Index.build(cobs.make_params(**kw), docs.bytes, docs.str_off, docs.doc_str)
+        assert e.value.status == cobs.EINVAL
+    gix = cobs.Index.build(cobs.make_params(0, 31, True, 1, 0.3, 0, 1), docs.bytes,
+                           docs.str_off, docs.doc_str)
+    data, off = queries_of([b"ACGT" * 10])
+    with pytest.raises(cobs.CobsError):
+        gix.query(data, off, k=(1, 0))
+    with pytest.raises(cobs.CobsError):
+        gix.query(data, off, score_bits=8)
+
+
+def test_config1_full_size():
+    # the classic 1,000-document workload at its full size: every query, every
+    # document, threshold 0.8 with 16-bit scores
+    w = synth.CONFIGS[1]
+    d = synth.docs(w)
+    qs = synth.dna_queries(w)
+    gix, oix = build_both(d, 0, w.q, w.canonical, w.h, w.p, w.B, w.hash_seed)
+    assert_same_index(gix, oix)
+    sc, l = gix.scores(qs.bytes, qs.q_off)
+    for i in range(qs.n):
+        want, wl = oix.query_scores(qs.get(i))
+        assert l[i] == wl and np.array_equal(sc[i], want), i
+    res = gix.query(qs.bytes, qs.q_off, k=w.k, topk=0, score_bits=16)
+    for i in range(qs.n):
+        ids, s, l = oix.query(qs.get(i), w.k[0], w.k[1], 0)
+        assert np.array_equal(res[i][0], ids) and np.array_equal(res[i][1], s)
