@@ -106,15 +106,15 @@ def cpu_baseline(w, synth, oracle, qs, budget_s):
     done_l, t0 = 0, time.perf_counter()
     i, nq = 0, qs.n
     with ThreadPoolExecutor(threads) as ex:
-        while time.perf_counter() - t0 < budget_s and i < nq:
-            batch = [qs.get(j) for j in range(i, min(nq, i + 4 * threads))]
+        while time.perf_counter() - t0 < budget_s:
+            batch = [qs.get(j % nq) for j in range(i, i + 4 * threads)]
             for sc, l in ex.map(ix.query_scores, batch):
                 done_l += l
             i += len(batch)
     dt = time.perf_counter() - t0
     rate = done_l * S / dt / w.n_docs
     return {"value": rate, "unit": "lookups/s", "cores": threads, "kind": "oracle",
-            "sample": f"{i} queries of the set against documents 0..{S - 1} (their own "
+            "sample": f"{i} queries (the set, cycled) against documents 0..{S - 1} (their own "
                       f"{'compact' if w.B else 'classic'} plan), {dt:.1f}s wall; "
                       f"rate scaled by {S}/{w.n_docs} documents"}
 
@@ -167,18 +167,18 @@ def main():
     q_off = qs.q_off
     k = w.k
 
-    for i in range(args.warmup):
-        res = ix.query(qdev, q_off, k=k, topk=0)
+    for i in range(max(args.warmup, 1)):
+        nt, hoff, ids, sc = ix.query_flat(qdev, q_off, k=k, topk=0)
         log(f"warmup {i + 1}/{args.warmup}")
-    lookups = sum(r[2] for r in res)
-    survivors = sum(len(r[0]) for r in res)
+    lookups = int(nt.sum())
+    survivors = int(len(ids))
 
     cobs.profile(True)
     cobs.profile_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        res = ix.query(qdev, q_off, k=k, topk=0)
+        ix.query_flat(qdev, q_off, k=k, topk=0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = cobs.profile_read(reset=True)
@@ -194,11 +194,11 @@ def main():
     # top-k run of the same set (K = 0, top-100)
     topk_ms = None
     if w.topk:
-        ix.query(qdev, q_off, k=(0, 1), topk=w.topk)
+        ix.query_flat(qdev, q_off, k=(0, 1), topk=w.topk)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(2):
-            ix.query(qdev, q_off, k=(0, 1), topk=w.topk)
+            ix.query_flat(qdev, q_off, k=(0, 1), topk=w.topk)
         torch.cuda.synchronize()
         topk_ms = (time.perf_counter() - t1) / 2 * 1e3
 
@@ -206,13 +206,13 @@ def main():
     npq = min(args.plain_queries, qs.n)
     sub = qs.subset(range(npq))
     subdev = torch.from_numpy(sub.bytes.copy()).to("cuda")
-    ix.query(subdev, sub.q_off, k=k, topk=0, mode=cobs.MODE_PLAIN)
+    ix.query_flat(subdev, sub.q_off, k=k, topk=0, mode=cobs.MODE_PLAIN)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    pr = ix.query(subdev, sub.q_off, k=k, topk=0, mode=cobs.MODE_PLAIN)
+    pnt = ix.query_flat(subdev, sub.q_off, k=k, topk=0, mode=cobs.MODE_PLAIN)[0]
     torch.cuda.synchronize()
     plain_dt = time.perf_counter() - t1
-    plain_rate = sum(r[2] for r in pr) / plain_dt
+    plain_rate = int(pnt.sum()) / plain_dt
     log(f"plain path: {npq} queries in {plain_dt:.3f}s")
 
     cpu = None

@@ -219,6 +219,24 @@ cobs_status cobs_query_terms(const cobs_index *ix, const uint8_t *bytes,
 
 void cobs_hits_free(cobs_hits *hits, uint32_t n);
 
+/*
+ * The same query batch as cobs_query_batch with the hits of all queries in
+ * one flat, library-owned result object (no per-query allocation).
+ */
+typedef struct cobs_results cobs_results;
+cobs_status cobs_query_results(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
+                               uint32_t n_queries, const cobs_query_opts *opts, void *stream,
+                               cobs_results **out);
+/*
+ * View of a result object: query i's hits are doc_id[hit_off[i] .. hit_off[i+1])
+ * with score[] alongside, ordered by (score desc, input id asc); num_terms[i]
+ * is l.  Pointers stay valid until cobs_results_free.
+ */
+cobs_status cobs_results_view(const cobs_results *r, uint32_t *n_queries,
+                              const uint32_t **num_terms, const uint64_t **hit_off,
+                              const uint32_t **doc_id, const uint32_t **score);
+void cobs_results_free(cobs_results *r);
+
 /* ---- serving ------------------------------------------------------------ */
 
 /*

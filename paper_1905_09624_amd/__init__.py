@@ -96,12 +96,22 @@ EXPORTS = {
     "cobs_query_terms": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
                                    C.c_void_p, C.c_void_p, C.c_void_p]),
     "cobs_hits_free": (None, [C.POINTER(Hits), C.c_uint32]),
+    "cobs_query_results": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                                     C.POINTER(QueryOpts), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "cobs_results_view": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32),
+                                    C.POINTER(C.POINTER(C.c_uint32)),
+                                    C.POINTER(C.POINTER(C.c_uint64)),
+                                    C.POINTER(C.POINTER(C.c_uint32)),
+                                    C.POINTER(C.POINTER(C.c_uint32))]),
+    "cobs_results_free": (None, [C.c_void_p]),
     "cobs_serve": (C.c_int, [C.c_void_p, C.POINTER(ServeOpts), C.POINTER(C.c_void_p)]),
     "cobs_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
                               C.c_uint32, C.c_uint64, C.POINTER(C.c_uint64)]),
     "cobs_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.POINTER(Hits)),
                             C.POINTER(C.c_uint64)]),
     "cobs_serve_stop": (C.c_int, [C.c_void_p, C.POINTER(ServeStats)]),
+    "cobs_serve_replay": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                    C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]),
     "cobs_profile": (C.c_int, [C.c_int]),
     "cobs_profile_read": (C.c_int, [C.POINTER(KernelTiming), C.c_int]),
     "cobs_last_error": (C.c_char_p, []),
@@ -241,9 +251,47 @@ class Index:
         _check(lib().cobs_index_read(self._h, offset, nbytes, _p(out)))
         return out[:nbytes]
 
+    def query_flat(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
+                   stream=None):
+        """Hits of every query in flat arrays: (num_terms[n], hit_off[n+1],
+        doc_ids[total], scores[total]); query i's hits are
+        doc_ids[hit_off[i]:hit_off[i+1]]."""
+        ptr, mem, keep = _byte_source(data)
+        qo = np.ascontiguousarray(q_off, dtype=np.uint64)
+        n = len(qo) - 1
+        opts = QueryOpts(k[0], k[1], topk, score_bits, mode, mem)
+        r = C.c_void_p()
+        _check(lib().cobs_query_results(self._h, ptr, _p(qo), n, C.byref(opts), _stream(stream),
+                                        C.byref(r)))
+        try:
+            nq = C.c_uint32()
+            nt, off, ids, sc = (C.POINTER(C.c_uint32)(), C.POINTER(C.c_uint64)(),
+                                C.POINTER(C.c_uint32)(), C.POINTER(C.c_uint32)())
+            _check(lib().cobs_results_view(r, C.byref(nq), C.byref(nt), C.byref(off),
+                                           C.byref(ids), C.byref(sc)))
+            num_terms = np.ctypeslib.as_array(nt, (n,)).copy() if n else np.zeros(0, np.uint32)
+            hit_off = np.ctypeslib.as_array(off, (n + 1,)).copy()
+            total = int(hit_off[-1])
+            if total:
+                doc_ids = np.ctypeslib.as_array(ids, (total,)).copy()
+                scores = np.ctypeslib.as_array(sc, (total,)).copy()
+            else:
+                doc_ids = np.zeros(0, np.uint32)
+                scores = np.zeros(0, np.uint32)
+            return num_terms, hit_off, doc_ids, scores
+        finally:
+            lib().cobs_results_free(r)
+
     def query(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
               stream=None):
         """Hits of every query: list of (doc_ids, scores, num_terms)."""
+        nt, off, ids, sc = self.query_flat(data, q_off, k, topk, score_bits, mode, stream)
+        return [(ids[off[i]:off[i + 1]], sc[off[i]:off[i + 1]], int(nt[i]))
+                for i in range(len(nt))]
+
+    def query_hits(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
+                   stream=None):
+        """The same through cobs_query_batch (one cobs_hits per query)."""
         ptr, mem, keep = _byte_source(data)
         qo = np.ascontiguousarray(q_off, dtype=np.uint64)
         n = len(qo) - 1
@@ -316,6 +364,21 @@ class Server:
             return ids, sc, int(h.num_terms), lat.value
         finally:
             lib().cobs_hits_free(out, 1)
+
+    def replay(self, data, q_off, arrival_s, k=(4, 5), topk=0):
+        """Open-loop replay: query i submitted at its scheduled arrival (seconds
+        from now) by a native thread; returns (latency_ns, n_hits) arrays."""
+        arr = np.ascontiguousarray(data, dtype=np.uint8)
+        if arr.size == 0:
+            arr = np.zeros(1, np.uint8)
+        qo = np.ascontiguousarray(q_off, dtype=np.uint64)
+        n = len(qo) - 1
+        at = np.ascontiguousarray(np.round(np.asarray(arrival_s) * 1e9), dtype=np.uint64)
+        lat = np.zeros(max(n, 1), np.uint64)
+        nh = np.zeros(max(n, 1), np.uint32)
+        _check(lib().cobs_serve_replay(self._h, C.c_void_p(arr.ctypes.data), _p(qo), n, _p(at),
+                                       k[0], k[1], topk, _p(lat), _p(nh)))
+        return lat[:n], nh[:n]
 
     def stop(self) -> dict:
         st = ServeStats()

@@ -32,8 +32,8 @@ def build(verbose: bool = False) -> str:
         if not os.path.exists(os.path.join(CSRC, src)):
             continue
         obj = os.path.join(objdir, src + ".o")
-        jobs.append([HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, src),
-                     "-o", obj])
+        jobs.append([HIPCC, *COMMON, *DEVICE, "--cuda-host-only", "-c",
+                     os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     procs = [subprocess.Popen(j, stdout=subprocess.PIPE, stderr=subprocess.STDOUT) for j in jobs]
     for j, p in zip(jobs, procs):

@@ -55,6 +55,15 @@ __device__ __forceinline__ uint64_t window_term(const uint8_t *s, const TermSpec
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// one lane's 16 bytes of a row slice; rows are read once per (term, query),
+// so they bypass the caches' retention (non-temporal)
+__device__ __forceinline__ u32x4 load_row(const uint8_t *p)
+{
+    return __builtin_nontemporal_load((const u32x4 *)p);
+}
+
 __device__ __forceinline__ uint64_t bcast64(uint64_t v)
 {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -353,7 +362,8 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
     const uint32_t lane = lane_id();
     const uint64_t total = *a.total_items;
     const uint32_t tchunks = a.chunk_prefix[a.n_queries];
-    constexpr int U = kH1 ? 8 : 4;
+    // row loads in flight per wavefront (h rows per term each)
+    constexpr int U = kH1 ? 16 : 4;
     Counter<P> cnt;
 
     for (;;) {
@@ -369,8 +379,18 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
         const SliceDesc sd = a.slices[sl];
         const uint32_t kbeg = chunk * a.chunk;
         const uint32_t kend = min(qn.ell, kbeg + a.chunk);
-        const bool act = lane * 16u < sd.width;
-        const uint8_t *mb = a.matrix + sd.base + lane * 16u;
+        // uniform slice geometry in SGPRs
+        const uint64_t sbase = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sd.base >> 32)) << 32) |
+                               __builtin_amdgcn_readfirstlane((uint32_t)sd.base);
+        const uint32_t sstride = __builtin_amdgcn_readfirstlane(sd.stride);
+        const uint32_t srows = __builtin_amdgcn_readfirstlane(sd.rows);
+        const uint32_t swidth = __builtin_amdgcn_readfirstlane(sd.width);
+        // every lane loads (no divergent loads: they serialise the memory
+        // pipeline); lanes past the slice width read an in-row address and
+        // mask the bits off
+        const uint32_t loff = min(lane * 16u, swidth - 16u);
+        const uint32_t lmask = lane * 16u < swidth ? ~0u : 0u;
+        const uint8_t *mrow0 = a.matrix + sbase + loff;
         const uint64_t *hp = a.hashes + qn.hbase * a.h;
 
         cnt.clear();
@@ -379,40 +399,47 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
             uint32_t r[kH1 ? 1 : kMaxHashes];
             if (lane < n) {
                 if (kH1) {
-                    r[0] = (uint32_t)(hp[k0 + lane] % sd.rows);
+                    r[0] = (uint32_t)(hp[k0 + lane] % srows);
                 } else {
 #pragma unroll
                     for (int i = 0; i < kMaxHashes; ++i)
-                        if (i < (int)a.h) r[i] = (uint32_t)(hp[(uint64_t)(k0 + lane) * a.h + i] % sd.rows);
+                        if (i < (int)a.h) r[i] = (uint32_t)(hp[(uint64_t)(k0 + lane) * a.h + i] % srows);
                 }
             }
-            for (uint32_t j = 0; j < n; j += U) {
-                uint32_t x[U][4];
+            uint32_t j = 0;
+            for (; j + U <= n; j += U) {
+                u32x4 v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (j + u < n) {
-                        if (kH1) {
-                            const uint32_t row = __builtin_amdgcn_readlane(r[0], j + u);
-                            uint4 v = make_uint4(0, 0, 0, 0);
-                            if (act) v = *(const uint4 *)(mb + (uint64_t)row * sd.stride);
-                            x[u][0] = v.x; x[u][1] = v.y; x[u][2] = v.z; x[u][3] = v.w;
-                        } else {
-                            x[u][0] = x[u][1] = x[u][2] = x[u][3] = ~0u;
+                    if (kH1) {
+                        const uint32_t row = __builtin_amdgcn_readlane(r[0], j + u);
+                        v[u] = load_row(mrow0 + (uint64_t)row * sstride);
+                    } else {
+                        v[u] = load_row(mrow0 + (uint64_t)__builtin_amdgcn_readlane(r[0], j + u) * sstride);
 #pragma unroll
-                            for (int i = 0; i < kMaxHashes; ++i) {
-                                if (i < (int)a.h) {
-                                    const uint32_t row = __builtin_amdgcn_readlane(r[i], j + u);
-                                    uint4 v = make_uint4(0, 0, 0, 0);
-                                    if (act) v = *(const uint4 *)(mb + (uint64_t)row * sd.stride);
-                                    x[u][0] &= v.x; x[u][1] &= v.y; x[u][2] &= v.z; x[u][3] &= v.w;
-                                }
-                            }
-                        }
+                        for (int i = 1; i < kMaxHashes; ++i)
+                            if (i < (int)a.h)
+                                v[u] &= load_row(mrow0 + (uint64_t)__builtin_amdgcn_readlane(r[i], j + u) * sstride);
                     }
                 }
+                // all U row loads in flight before the first is consumed
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (j + u < n) cnt.add(x[u]);
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t x[4] = {v[u].x & lmask, v[u].y & lmask, v[u].z & lmask, v[u].w & lmask};
+                    cnt.add(x);
+                }
+            }
+            for (; j < n; ++j) {
+                u32x4 v = load_row(mrow0 + (uint64_t)__builtin_amdgcn_readlane(r[0], j) * sstride);
+                if (!kH1) {
+#pragma unroll
+                    for (int i = 1; i < kMaxHashes; ++i)
+                        if (i < (int)a.h)
+                            v &= load_row(mrow0 + (uint64_t)__builtin_amdgcn_readlane(r[i], j) * sstride);
+                }
+                const uint32_t x[4] = {v.x & lmask, v.y & lmask, v.z & lmask, v.w & lmask};
+                cnt.add(x);
             }
         }
         if (cnt.n) cnt.flush();

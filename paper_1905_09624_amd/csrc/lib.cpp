@@ -850,17 +850,25 @@ void cobs_hits_free(cobs_hits *hits, uint32_t n)
     std::free(hits);
 }
 
-cobs_status cobs_query_batch(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
-                             uint32_t n_queries, const cobs_query_opts *opts, void *stream,
-                             cobs_hits **out)
+}  // extern "C"
+
+struct cobs_results {
+    std::vector<uint32_t> num_terms;
+    std::vector<uint64_t> off;
+    std::vector<uint32_t> ids, scores;
+};
+
+namespace {
+
+// Batched: one pipeline run over all queries.  Plain: one run per query.
+// sink(batch output, first query of the batch, queries in the batch).
+template <typename Sink>
+cobs_status query_driver(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
+                         uint32_t n_queries, const cobs_query_opts *opts, void *stream, Sink sink)
 {
-    if (!ix || !opts || !out) return set_error(COBS_EINVAL, "NULL argument");
-    *out = nullptr;
     if (opts->mode != COBS_MODE_BATCHED && opts->mode != COBS_MODE_PLAIN)
         return set_error(COBS_EINVAL, "unknown mode");
     hipStream_t st = (hipStream_t)stream;
-    cobs_hits *hits = (cobs_hits *)std::calloc(std::max<uint32_t>(n_queries, 1), sizeof(cobs_hits));
-    if (!hits) return set_error(COBS_ENOMEM, "out of host memory");
     Workspace *ws = acquire_workspace(ix);
     BatchSpec spec;
     spec.bytes = bytes;
@@ -875,17 +883,35 @@ cobs_status cobs_query_batch(cobs_index *ix, const uint8_t *bytes, const uint64_
         spec.q_off = q_off;
         spec.n = n_queries;
         s = run_batch(ix, *ws, spec, st, bo);
-        if (s == COBS_OK) s = make_hits(bo, 0, n_queries, hits);
+        if (s == COBS_OK) s = sink(bo, 0u, n_queries);
     } else {
-        // one query per launch of the pipeline
         for (uint32_t i = 0; i < n_queries && s == COBS_OK; ++i) {
             spec.q_off = q_off + i;
             spec.n = 1;
             s = run_batch(ix, *ws, spec, st, bo);
-            if (s == COBS_OK) s = make_hits(bo, 0, 1, hits + i);
+            if (s == COBS_OK) s = sink(bo, i, 1u);
         }
     }
     release_workspace(ix, ws);
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+cobs_status cobs_query_batch(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
+                             uint32_t n_queries, const cobs_query_opts *opts, void *stream,
+                             cobs_hits **out)
+{
+    if (!ix || !opts || !out) return set_error(COBS_EINVAL, "NULL argument");
+    *out = nullptr;
+    cobs_hits *hits = (cobs_hits *)std::calloc(std::max<uint32_t>(n_queries, 1), sizeof(cobs_hits));
+    if (!hits) return set_error(COBS_ENOMEM, "out of host memory");
+    cobs_status s = query_driver(ix, bytes, q_off, n_queries, opts, stream,
+                                 [&](const BatchOut &bo, uint32_t q0, uint32_t n) {
+                                     return make_hits(bo, 0, n, hits + q0);
+                                 });
     if (s != COBS_OK) {
         cobs_hits_free(hits, n_queries);
         return s;
@@ -893,6 +919,49 @@ cobs_status cobs_query_batch(cobs_index *ix, const uint8_t *bytes, const uint64_
     *out = hits;
     return COBS_OK;
 }
+
+cobs_status cobs_query_results(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
+                               uint32_t n_queries, const cobs_query_opts *opts, void *stream,
+                               cobs_results **out)
+{
+    if (!ix || !opts || !out) return set_error(COBS_EINVAL, "NULL argument");
+    *out = nullptr;
+    auto *r = new cobs_results();
+    r->num_terms.assign(n_queries, 0);
+    r->off.assign((size_t)n_queries + 1, 0);
+    cobs_status s = query_driver(ix, bytes, q_off, n_queries, opts, stream,
+                                 [&](const BatchOut &bo, uint32_t q0, uint32_t n) {
+                                     const uint64_t base = r->ids.size(), tot = bo.start[n];
+                                     r->ids.insert(r->ids.end(), bo.ids, bo.ids + tot);
+                                     r->scores.insert(r->scores.end(), bo.scores, bo.scores + tot);
+                                     for (uint32_t i = 0; i < n; ++i) {
+                                         r->num_terms[q0 + i] = bo.num_terms[i];
+                                         r->off[q0 + i + 1] = base + bo.start[i + 1];
+                                     }
+                                     return COBS_OK;
+                                 });
+    if (s != COBS_OK) {
+        delete r;
+        return s;
+    }
+    *out = r;
+    return COBS_OK;
+}
+
+cobs_status cobs_results_view(const cobs_results *r, uint32_t *n_queries,
+                              const uint32_t **num_terms, const uint64_t **hit_off,
+                              const uint32_t **doc_id, const uint32_t **score)
+{
+    if (!r) return set_error(COBS_EINVAL, "results is NULL");
+    if (n_queries) *n_queries = (uint32_t)r->num_terms.size();
+    if (num_terms) *num_terms = r->num_terms.data();
+    if (hit_off) *hit_off = r->off.data();
+    if (doc_id) *doc_id = r->ids.data();
+    if (score) *score = r->scores.data();
+    return COBS_OK;
+}
+
+void cobs_results_free(cobs_results *r) { delete r; }
 
 cobs_status cobs_query_scores(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
                               uint32_t n_queries, uint32_t mem, void *stream, uint32_t *scores,

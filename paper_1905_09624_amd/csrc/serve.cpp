@@ -9,6 +9,8 @@
 // next worker collects the requests that arrived meanwhile, so new arrivals
 // join the next batch instead of waiting for a queue to drain.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>

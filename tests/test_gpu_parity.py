@@ -248,6 +248,31 @@ def test_long_query_multi_chunk_and_global_table():
     check_queries(gix, oix, data, off, k=(0, 1), topk=7, mode=1)
 
 
+def test_hits_and_flat_results_agree(workload):
+    # cobs_query_batch (one cobs_hits per query) and cobs_query_results (flat)
+    w, d, qs, gix, oix = workload
+    for mode in (0, 1):
+        a = gix.query_hits(qs.bytes, qs.q_off, k=(1, 2), topk=5, mode=mode)
+        b = gix.query(qs.bytes, qs.q_off, k=(1, 2), topk=5, mode=mode)
+        assert len(a) == len(b) == qs.n
+        for x, y in zip(a, b):
+            assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) and x[2] == y[2]
+
+
+def test_device_resident_queries():
+    import torch
+    cobs = _cobs()
+    w = synth.CONFIGS[3].scaled(500)
+    d = synth.docs(w)
+    qs = synth.dna_queries(w, n=12)
+    prm = cobs.make_params(0, w.q, w.canonical, w.h, w.p, w.B, w.hash_seed)
+    gix = cobs.Index.build(prm, d.bytes, d.str_off, d.doc_str)
+    host = gix.query(qs.bytes, qs.q_off, k=(1, 2))
+    dev = gix.query(torch.from_numpy(qs.bytes.copy()).cuda(), qs.q_off, k=(1, 2))
+    for x, y in zip(host, dev):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) and x[2] == y[2]
+
+
 def test_score_width_overflow():
     cobs = _cobs()
     rng = np.random.default_rng(9)
