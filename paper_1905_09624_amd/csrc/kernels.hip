@@ -64,10 +64,22 @@ __device__ __forceinline__ u32x4 load_row(const uint8_t *p)
     return __builtin_nontemporal_load((const u32x4 *)p);
 }
 
+// The lane builtins return int: convert to uint32_t before any widening, or
+// a value with bit 31 set is sign-extended into the upper word.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, uint32_t l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+
 __device__ __forceinline__ uint64_t bcast64(uint64_t v)
 {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    const uint32_t lo = uniform_u32((uint32_t)v);
+    const uint32_t hi = uniform_u32((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
 
@@ -76,7 +88,7 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return __builtin_amdgcn_readfirstlane(v);
+    return uniform_u32(v);
 }
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v)
@@ -380,11 +392,10 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
         const uint32_t kbeg = chunk * a.chunk;
         const uint32_t kend = min(qn.ell, kbeg + a.chunk);
         // uniform slice geometry in SGPRs
-        const uint64_t sbase = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sd.base >> 32)) << 32) |
-                               __builtin_amdgcn_readfirstlane((uint32_t)sd.base);
-        const uint32_t sstride = __builtin_amdgcn_readfirstlane(sd.stride);
-        const uint32_t srows = __builtin_amdgcn_readfirstlane(sd.rows);
-        const uint32_t swidth = __builtin_amdgcn_readfirstlane(sd.width);
+        const uint64_t sbase = bcast64(sd.base);
+        const uint32_t sstride = uniform_u32(sd.stride);
+        const uint32_t srows = uniform_u32(sd.rows);
+        const uint32_t swidth = uniform_u32(sd.width);
         // every lane loads (no divergent loads: they serialise the memory
         // pipeline); lanes past the slice width read an in-row address and
         // mask the bits off
@@ -412,14 +423,14 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (kH1) {
-                        const uint32_t row = __builtin_amdgcn_readlane(r[0], j + u);
+                        const uint32_t row = lane_u32(r[0], j + u);
                         v[u] = load_row(mrow0 + (uint64_t)row * sstride);
                     } else {
-                        v[u] = load_row(mrow0 + (uint64_t)__builtin_amdgcn_readlane(r[0], j + u) * sstride);
+                        v[u] = load_row(mrow0 + (uint64_t)lane_u32(r[0], j + u) * sstride);
 #pragma unroll
                         for (int i = 1; i < kMaxHashes; ++i)
                             if (i < (int)a.h)
-                                v[u] &= load_row(mrow0 + (uint64_t)__builtin_amdgcn_readlane(r[i], j + u) * sstride);
+                                v[u] &= load_row(mrow0 + (uint64_t)lane_u32(r[i], j + u) * sstride);
                     }
                 }
                 // all U row loads in flight before the first is consumed
@@ -431,12 +442,12 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
                 }
             }
             for (; j < n; ++j) {
-                u32x4 v = load_row(mrow0 + (uint64_t)__builtin_amdgcn_readlane(r[0], j) * sstride);
+                u32x4 v = load_row(mrow0 + (uint64_t)lane_u32(r[0], j) * sstride);
                 if (!kH1) {
 #pragma unroll
                     for (int i = 1; i < kMaxHashes; ++i)
                         if (i < (int)a.h)
-                            v &= load_row(mrow0 + (uint64_t)__builtin_amdgcn_readlane(r[i], j) * sstride);
+                            v &= load_row(mrow0 + (uint64_t)lane_u32(r[i], j) * sstride);
                 }
                 const uint32_t x[4] = {v.x & lmask, v.y & lmask, v.z & lmask, v.w & lmask};
                 cnt.add(x);
@@ -455,7 +466,7 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
             __threadfence();
             uint32_t tk = 0;
             if (lane == 0) tk = atomicAdd(&a.tickets[(uint64_t)qi * a.n_slices + sl], 1u);
-            tk = __builtin_amdgcn_readfirstlane(tk);
+            tk = uniform_u32(tk);
             if (tk != qn.nch - 1) continue;
             __threadfence();
             if (lane == 0) a.tickets[(uint64_t)qi * a.n_slices + sl] = 0;   // ready for reuse
@@ -700,7 +711,7 @@ __global__ __launch_bounds__(256) void count_kernel(const uint8_t *bytes, const 
                                          &empty_flag[d]);
             }
         }
-        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const uint32_t d0 = uniform_u32(d);
         const bool same = __all((w >= W) || d == d0);
         const unsigned long long m = __ballot(uniq);
         if (same) {

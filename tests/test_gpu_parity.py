@@ -273,6 +273,39 @@ def test_device_resident_queries():
         assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) and x[2] == y[2]
 
 
+def test_block_offsets_beyond_2_and_4_gib():
+    # Regression: slice base offsets with bit 31 (and bit 32) set must not be
+    # sign-extended.  p = 1e-5 inflates the filters: three one-document
+    # blocks of ~2.6-3.1 GB, so blocks 1 and 2 start past 2^31 and 2^32 bytes.
+    rng = np.random.default_rng(31)
+    lists = [rand_dna(rng, 230), rand_dna(rng, 250), rand_dna(rng, 270)]
+    d = oracle.Docs.from_lists(lists)
+    gix, oix = build_both(d, 0, 31, True, 1, 1e-5, 1, 17)
+    offs = [gix.block(b)["offset"] for b in range(3)]
+    assert offs[1] >= 2**31 and offs[2] >= 2**32
+    for b in range(3):
+        gb, ob = gix.block(b), oix.block(b)
+        assert (gb["rows"], gb["stride"], gb["docs"]) == (ob["rows"], ob["stride"], ob["docs"])
+    # the rows the oracle set, read back from the device
+    omat_bits = oix.matrix()
+    for b in range(3):
+        ob = oix.block(b)
+        blk = omat_bits[ob["offset"]:ob["offset"] + ob["rows"] * ob["stride"]].reshape(ob["rows"], ob["stride"])
+        rows = np.nonzero(blk[:, 0])[0]
+        assert len(rows) > 150
+        for r in rows[:20]:
+            got = gix.read(gix.block(b)["offset"] + int(r) * ob["stride"], ob["stride"])
+            assert np.array_equal(got, blk[r])
+    qs = lists + [lists[1][10:200], lists[2][:100] + rand_dna(rng, 60), rand_dna(rng, 300)]
+    data, off = queries_of(qs)
+    sc, l = gix.scores(data, off)
+    for i, s in enumerate(qs):
+        want, wl = oix.query_scores(s)
+        assert l[i] == wl and np.array_equal(sc[i], want), i
+    check_queries(gix, oix, data, off, k=(4, 5), topk=0, mode=0)
+    check_queries(gix, oix, data, off, k=(0, 1), topk=2, mode=1)
+
+
 def test_score_width_overflow():
     cobs = _cobs()
     rng = np.random.default_rng(9)
