@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk-gb", type=float, default=8.0,
                     help="device bytes of documents generated per build run")
+    ap.add_argument("--calib-copy-gb", type=float, default=0.0,
+                    help="run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
 
 
@@ -163,6 +165,26 @@ def main():
     log(f"index built in {build_s:.1f}s: {info['n_blocks']} blocks, "
         f"{info['total_bytes'] / 1e9:.2f} GB, {row_bytes_per_term} row bytes per term-hash")
 
+    if args.calib_copy_gb > 0:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE
+        # counters calibrate the counter units of a --pmc run
+        nb = int(args.calib_copy_gb * 2**30)
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {nb} bytes done")
+        del src, dst
+
+    # autotune the gather launch shape on a separate query set of the same shape
+    if w.kind == "dna":
+        tq = synth.dna_queries(w, n=qs.n, first=qs.n)
+    else:
+        tq = synth.text_queries(w, d, n=qs.n)
+    tuning = ix.tune(torch.from_numpy(tq.bytes.copy()).to("cuda"), tq.q_off)
+    log(f"tuned: {tuning}")
+
     qdev = torch.from_numpy(qs.bytes.copy()).to("cuda")     # resident in HBM
     q_off = qs.q_off
     k = w.k
@@ -247,6 +269,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
         },
         "gather_kernel_ms": gather_ms,
+        "tuning": tuning,
         "gather_row_bytes_per_launch": gather_bytes,
         "survivors_per_step": survivors,
         "topk100_ms_per_step": topk_ms,

@@ -296,6 +296,28 @@ cobs_status cobs_serve_replay(cobs_server *s, const uint8_t *bytes, const uint64
                               uint32_t k_den, uint32_t topk, uint64_t *latency_ns,
                               uint32_t *n_hits);
 
+/* ---- tuning --------------------------------------------------------------- */
+
+/*
+ * Launch shape of the gather kernel for an index: `unroll` terms whose rows
+ * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4) and `chunk`
+ * distinct terms per work item (longer queries are split and their partial
+ * counters merged).  0 = automatic.  Results never depend on either.
+ */
+typedef struct {
+    uint32_t unroll;
+    uint32_t chunk;
+    double gather_ms;    /* cobs_tune: the chosen shape's gather time */
+} cobs_tuning;
+
+/* Time the gather kernel on the sample batch for every supported
+ * (unroll, chunk) pair, keep the fastest for this index, report it in *best.
+ * The sample should resemble the batches to come (a separate query set). */
+cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
+                      uint32_t n_queries, uint32_t mem, void *stream, cobs_tuning *best);
+/* Set (or, with zeros, reset) the launch shape explicitly. */
+cobs_status cobs_set_tuning(cobs_index *ix, const cobs_tuning *t);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /*

@@ -69,6 +69,10 @@ class ServeStats(C.Structure):
                 ("lookups_per_s", C.c_double), ("wall_s", C.c_double), ("lookups", C.c_uint64)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("unroll", C.c_uint32), ("chunk", C.c_uint32), ("gather_ms", C.c_double)]
+
+
 class KernelTiming(C.Structure):
     _fields_ = [("launches", C.c_uint64), ("total_ms", C.c_double), ("last_ms", C.c_double),
                 ("row_bytes", C.c_uint64), ("terms", C.c_uint64)]
@@ -112,6 +116,9 @@ EXPORTS = {
     "cobs_serve_stop": (C.c_int, [C.c_void_p, C.POINTER(ServeStats)]),
     "cobs_serve_replay": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                     C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "cobs_tune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
+                            C.c_void_p, C.POINTER(Tuning)]),
+    "cobs_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
     "cobs_profile": (C.c_int, [C.c_int]),
     "cobs_profile_read": (C.c_int, [C.POINTER(KernelTiming), C.c_int]),
     "cobs_last_error": (C.c_char_p, []),
@@ -250,6 +257,19 @@ class Index:
         out = np.zeros(max(nbytes, 1), np.uint8)
         _check(lib().cobs_index_read(self._h, offset, nbytes, _p(out)))
         return out[:nbytes]
+
+    def tune(self, data, q_off, stream=None) -> dict:
+        """Autotune the gather launch shape on a sample batch (kept by the index)."""
+        ptr, mem, keep = _byte_source(data)
+        qo = np.ascontiguousarray(q_off, dtype=np.uint64)
+        t = Tuning()
+        _check(lib().cobs_tune(self._h, ptr, _p(qo), len(qo) - 1, mem, _stream(stream),
+                               C.byref(t)))
+        return dict(unroll=t.unroll, chunk=t.chunk, gather_ms=t.gather_ms)
+
+    def set_tuning(self, unroll=0, chunk=0) -> None:
+        t = Tuning(unroll, chunk, 0.0)
+        _check(lib().cobs_set_tuning(self._h, C.byref(t)))
 
     def query_flat(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
                    stream=None):

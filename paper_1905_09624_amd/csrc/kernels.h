@@ -108,9 +108,13 @@ hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, uint32_t n
                        hipStream_t st);
 
 // a5-a8: persistent gather / AND / ADD / threshold-or-top-k kernel.
-hipError_t launch_gather(const GatherArgs &a, int planes, int grid, hipStream_t st);
-int gather_planes_for(uint64_t max_terms);   // template plane count to use
-int gather_grid(int planes, int h);           // persistent grid size
+// planes: counter planes (>= bits of the largest l); unroll: terms whose rows
+// are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4).
+hipError_t launch_gather(const GatherArgs &a, int planes, int unroll, int grid, hipStream_t st);
+int gather_planes_for(uint64_t max_terms);        // instantiated plane count to use
+int gather_default_unroll(int h);
+bool gather_unroll_valid(int unroll, int h);
+int gather_grid(int planes, int unroll, int h);   // persistent grid: CUs x resident blocks
 
 // a8+a9 ordering: group candidates by query and sort each query's segment by
 // (score desc, input id asc); write the first min(count, topk) hits.

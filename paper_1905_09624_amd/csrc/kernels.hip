@@ -262,13 +262,22 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, cons
 
 // ---- a5-a8: gather / AND / ADD / threshold-or-top-k -------------------------------------
 
-// bit-sliced counter: L holds a 4-bit low part (at most 15 adds between
-// flushes), H the P-bit total; each lane owns 4 dwords = 128 documents
+// full adder on 32 independent bit positions: a + b + c = s + 2 carry
+__device__ __forceinline__ void csa(uint32_t &s, uint32_t &carry, uint32_t a, uint32_t b, uint32_t c)
+{
+    const uint32_t u = a ^ b;
+    s = u ^ c;
+    carry = (a & b) | (u & c);
+}
+
+// Bit-sliced per-document counters of one wavefront slice: plane p holds bit
+// p of the score of every document; each lane owns 4 dwords = 128 documents.
+// A group of U indicator vectors is added through a carry-save adder tree
+// (ones, twos, fours planes absorb the inputs), and only the tree's single
+// carry vector ripples into the higher planes.
 template <int P>
 struct Counter {
     uint32_t H[P][4];
-    uint32_t L[4][4];
-    uint32_t n;
 
     __device__ __forceinline__ void clear()
     {
@@ -276,67 +285,76 @@ struct Counter {
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int d = 0; d < 4; ++d) H[p][d] = 0;
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-            for (int d = 0; d < 4; ++d) L[p][d] = 0;
-        n = 0;
     }
 
-    __device__ __forceinline__ void flush()
+    __device__ __forceinline__ void ripple(int d, int from, uint32_t c)
     {
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            uint32_t c = 0;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const uint32_t h = H[p][d], l = L[p][d], x = h ^ l;
-                H[p][d] = x ^ c;
-                c = (h & l) | (c & x);
-                L[p][d] = 0;
-            }
-#pragma unroll
-            for (int p = 4; p < P; ++p) {
-                const uint32_t h = H[p][d];
-                H[p][d] = h ^ c;
-                c = h & c;
-            }
-        }
-        n = 0;
-    }
-
-    // add one indicator vector (1 bit per document)
-    __device__ __forceinline__ void add(const uint32_t x[4])
-    {
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            uint32_t c = x[d], t;
-            t = L[0][d] & c; L[0][d] ^= c; c = t;
-            t = L[1][d] & c; L[1][d] ^= c; c = t;
-            t = L[2][d] & c; L[2][d] ^= c; c = t;
-            L[3][d] ^= c;
-        }
-        if (++n == 15) flush();
-    }
-
-    // add another full P-bit counter y (plane p, dword d)
-    __device__ __forceinline__ void add_planes(const uint4 *y)
-    {
-        uint32_t Y[P][4];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const uint4 v = y[p * 64];
-            Y[p][0] = v.x; Y[p][1] = v.y; Y[p][2] = v.z; Y[p][3] = v.w;
+            if (p < from) continue;
+            const uint32_t h = H[p][d];
+            H[p][d] = h ^ c;
+            c = h & c;
         }
+    }
+
+    // add U (1, 2, 4 or 8) indicator vectors
+    template <int U>
+    __device__ __forceinline__ void add(const u32x4 *x)
+    {
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
-            uint32_t c = 0;
+            uint32_t xs[U];
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const uint32_t h = H[p][d], l = Y[p][d], x = h ^ l;
-                H[p][d] = x ^ c;
-                c = (h & l) | (c & x);
+            for (int u = 0; u < U; ++u) xs[u] = x[u][d];
+            if constexpr (U == 1) {
+                ripple(d, 0, xs[0]);
+            } else if constexpr (U == 2) {
+                uint32_t t0;
+                csa(H[0][d], t0, H[0][d], xs[0], xs[1]);
+                ripple(d, 1, t0);
+            } else if constexpr (U == 4) {
+                uint32_t t0, t1, e;
+                csa(H[0][d], t0, H[0][d], xs[0], xs[1]);
+                csa(H[0][d], t1, H[0][d], xs[2], xs[3]);
+                csa(H[1][d], e, H[1][d], t0, t1);
+                ripple(d, 2, e);
+            } else {
+                static_assert(U == 8, "U must be 1, 2, 4 or 8");
+                uint32_t t0, t1, t2, t3, u0, u1, e;
+                csa(H[0][d], t0, H[0][d], xs[0], xs[1]);
+                csa(H[0][d], t1, H[0][d], xs[2], xs[3]);
+                csa(H[1][d], u0, H[1][d], t0, t1);
+                csa(H[0][d], t2, H[0][d], xs[4], xs[5]);
+                csa(H[0][d], t3, H[0][d], xs[6], xs[7]);
+                csa(H[1][d], u1, H[1][d], t2, t3);
+                csa(H[2][d], e, H[2][d], u0, u1);
+                ripple(d, 3, e);
             }
+        }
+    }
+
+    // add another P-plane counter stored plane-major (64 lanes x 16 B per
+    // plane); at most 4 of its planes are held in registers at a time, so the
+    // merge does not raise the kernel's register count
+    __device__ __forceinline__ void add_planes(const uint4 *y)
+    {
+        uint32_t c[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int p0 = 0; p0 < P; p0 += 4) {
+            uint4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (p0 + k < P) v[k] = y[(p0 + k) * 64];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (p0 + k < P) {
+                    const uint32_t yv[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) csa(H[p0 + k][d], c[d], H[p0 + k][d], yv[d], c[d]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 
@@ -368,14 +386,13 @@ struct Counter {
     }
 };
 
-template <int P, bool kH1>
+// U: terms whose rows are in flight per wavefront (h rows each)
+template <int P, int U, bool kH1>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 {
     const uint32_t lane = lane_id();
     const uint64_t total = *a.total_items;
     const uint32_t tchunks = a.chunk_prefix[a.n_queries];
-    // row loads in flight per wavefront (h rows per term each)
-    constexpr int U = kH1 ? 16 : 4;
     Counter<P> cnt;
 
     for (;;) {
@@ -417,43 +434,29 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
                         if (i < (int)a.h) r[i] = (uint32_t)(hp[(uint64_t)(k0 + lane) * a.h + i] % srows);
                 }
             }
-            uint32_t j = 0;
-            for (; j + U <= n; j += U) {
+            for (uint32_t j = 0; j < n; j += U) {
+                // a short last group repeats its last row (already in flight,
+                // served by the cache) and masks the repeats off
+                const uint32_t rem = n - j;
                 u32x4 v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (kH1) {
-                        const uint32_t row = lane_u32(r[0], j + u);
-                        v[u] = load_row(mrow0 + (uint64_t)row * sstride);
-                    } else {
-                        v[u] = load_row(mrow0 + (uint64_t)lane_u32(r[0], j + u) * sstride);
+                    const uint32_t t = j + min((uint32_t)u, rem - 1);
+                    v[u] = load_row(mrow0 + (uint64_t)lane_u32(r[0], t) * sstride);
+                    if (!kH1) {
 #pragma unroll
                         for (int i = 1; i < kMaxHashes; ++i)
                             if (i < (int)a.h)
-                                v[u] &= load_row(mrow0 + (uint64_t)lane_u32(r[i], j + u) * sstride);
+                                v[u] &= load_row(mrow0 + (uint64_t)lane_u32(r[i], t) * sstride);
                     }
                 }
                 // all U row loads in flight before the first is consumed
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t x[4] = {v[u].x & lmask, v[u].y & lmask, v[u].z & lmask, v[u].w & lmask};
-                    cnt.add(x);
-                }
-            }
-            for (; j < n; ++j) {
-                u32x4 v = load_row(mrow0 + (uint64_t)lane_u32(r[0], j) * sstride);
-                if (!kH1) {
-#pragma unroll
-                    for (int i = 1; i < kMaxHashes; ++i)
-                        if (i < (int)a.h)
-                            v &= load_row(mrow0 + (uint64_t)lane_u32(r[i], j) * sstride);
-                }
-                const uint32_t x[4] = {v.x & lmask, v.y & lmask, v.z & lmask, v.w & lmask};
-                cnt.add(x);
+                for (int u = 0; u < U; ++u) v[u] &= ((uint32_t)u < rem) ? lmask : 0u;
+                cnt.template add<U>(v);
             }
         }
-        if (cnt.n) cnt.flush();
 
         // several chunks of one (query, slice): the last to finish merges
         if (qn.nch > 1) {
@@ -470,8 +473,11 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
             if (tk != qn.nch - 1) continue;
             __threadfence();
             if (lane == 0) a.tickets[(uint64_t)qi * a.n_slices + sl] = 0;   // ready for reuse
+            // sum every chunk's partial, this wavefront's own included, into a
+            // cleared counter (merging into the live one makes the compiler
+            // keep a second copy of the planes)
+            cnt.clear();
             for (uint32_t c2 = 0; c2 < qn.nch; ++c2) {
-                if (c2 == chunk) continue;
                 const uint4 *other = (const uint4 *)(a.partials +
                                      ((uint64_t)(qn.pbase + c2) * a.n_slices + sl) * plane_words);
                 cnt.add_planes(other + lane);
@@ -767,14 +773,38 @@ int grid_for(uint64_t n, int block)
     return (int)g;
 }
 
+// Instantiated variants: h = 1 with 4 or 8 terms in flight, h > 1 with 2 or
+// 4 (each term then has h rows in flight).
 template <int P>
-hipError_t launch_gather_p(const GatherArgs &a, int grid, hipStream_t st)
+hipError_t launch_gather_p(const GatherArgs &a, int unroll, int grid, hipStream_t st)
 {
-    if (a.h == 1)
-        hipLaunchKernelGGL((gather_kernel<P, true>), dim3(grid), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((gather_kernel<P, false>), dim3(grid), dim3(256), 0, st, a);
+    if (a.h == 1) {
+        if (unroll == 8)
+            hipLaunchKernelGGL((gather_kernel<P, 8, true>), dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((gather_kernel<P, 4, true>), dim3(grid), dim3(256), 0, st, a);
+    } else {
+        if (unroll == 4)
+            hipLaunchKernelGGL((gather_kernel<P, 4, false>), dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((gather_kernel<P, 2, false>), dim3(grid), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
+}
+
+template <int P>
+int occ_of_p(int unroll, int h)
+{
+    int blocks = 0;
+    hipError_t e;
+    if (h == 1)
+        e = unroll == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 8, true>, 256, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 4, true>, 256, 0);
+    else
+        e = unroll == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 4, false>, 256, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 2, false>, 256, 0);
+    if (e != hipSuccess || blocks < 1) blocks = 1;
+    return blocks;
 }
 
 }  // namespace
@@ -816,38 +846,34 @@ int gather_planes_for(uint64_t max_terms)
 {
     int bits = 0;
     while (bits < 64 && (max_terms >> bits) != 0) ++bits;
-    if (bits <= 8) return 8;
-    if (bits <= 12) return 12;
-    if (bits <= 16) return 16;
-    if (bits <= 20) return 20;
-    if (bits <= 24) return 24;
+    for (int p : {8, 10, 12, 14, 16, 20, 24})
+        if (bits <= p) return p;
     return 32;
 }
 
-hipError_t launch_gather(const GatherArgs &a, int planes, int grid, hipStream_t st)
+int gather_default_unroll(int h) { return h == 1 ? 8 : 2; }
+
+bool gather_unroll_valid(int unroll, int h)
+{
+    return h == 1 ? (unroll == 4 || unroll == 8) : (unroll == 2 || unroll == 4);
+}
+
+hipError_t launch_gather(const GatherArgs &a, int planes, int unroll, int grid, hipStream_t st)
 {
     switch (planes) {
-    case 8: return launch_gather_p<8>(a, grid, st);
-    case 12: return launch_gather_p<12>(a, grid, st);
-    case 16: return launch_gather_p<16>(a, grid, st);
-    case 20: return launch_gather_p<20>(a, grid, st);
-    case 24: return launch_gather_p<24>(a, grid, st);
-    case 32: return launch_gather_p<32>(a, grid, st);
+    case 8: return launch_gather_p<8>(a, unroll, grid, st);
+    case 10: return launch_gather_p<10>(a, unroll, grid, st);
+    case 12: return launch_gather_p<12>(a, unroll, grid, st);
+    case 14: return launch_gather_p<14>(a, unroll, grid, st);
+    case 16: return launch_gather_p<16>(a, unroll, grid, st);
+    case 20: return launch_gather_p<20>(a, unroll, grid, st);
+    case 24: return launch_gather_p<24>(a, unroll, grid, st);
+    case 32: return launch_gather_p<32>(a, unroll, grid, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int P, bool H1>
-static int occ_of()
-{
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, H1>, 256, 0) !=
-        hipSuccess)
-        blocks = 1;
-    return blocks < 1 ? 1 : blocks;
-}
-
-int gather_grid(int planes, int h)
+int gather_grid(int planes, int unroll, int h)
 {
     static int cus = 0;
     if (!cus) {
@@ -857,14 +883,15 @@ int gather_grid(int planes, int h)
         if (cus <= 0) cus = 256;
     }
     int occ = 1;
-    const bool h1 = h == 1;
     switch (planes) {
-    case 8: occ = h1 ? occ_of<8, true>() : occ_of<8, false>(); break;
-    case 12: occ = h1 ? occ_of<12, true>() : occ_of<12, false>(); break;
-    case 16: occ = h1 ? occ_of<16, true>() : occ_of<16, false>(); break;
-    case 20: occ = h1 ? occ_of<20, true>() : occ_of<20, false>(); break;
-    case 24: occ = h1 ? occ_of<24, true>() : occ_of<24, false>(); break;
-    default: occ = h1 ? occ_of<32, true>() : occ_of<32, false>(); break;
+    case 8: occ = occ_of_p<8>(unroll, h); break;
+    case 10: occ = occ_of_p<10>(unroll, h); break;
+    case 12: occ = occ_of_p<12>(unroll, h); break;
+    case 14: occ = occ_of_p<14>(unroll, h); break;
+    case 16: occ = occ_of_p<16>(unroll, h); break;
+    case 20: occ = occ_of_p<20>(unroll, h); break;
+    case 24: occ = occ_of_p<24>(unroll, h); break;
+    default: occ = occ_of_p<32>(unroll, h); break;
     }
     return cus * occ;
 }

@@ -627,8 +627,10 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         if (cap > kLdsTableSlots) { tb[i] = tslots; tslots += cap; }
     }
     const int planes = gather_planes_for(maxw);
-    const int grid = gather_grid(planes, (int)h);
-    const uint32_t C = b.chunk ? b.chunk : auto_chunk(W, n, n_slices, grid);
+    int unroll = b.unroll ? (int)b.unroll : (ix->tuned_unroll ? ix->tuned_unroll : gather_default_unroll((int)h));
+    if (!gather_unroll_valid(unroll, (int)h)) unroll = gather_default_unroll((int)h);
+    const int grid = gather_grid(planes, unroll, (int)h);
+    const uint32_t C = b.chunk ? b.chunk : (ix->tuned_chunk ? ix->tuned_chunk : auto_chunk(W, n, n_slices, grid));
     uint64_t pslots = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t nw = wbase[i + 1] - wbase[i];
@@ -731,17 +733,20 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         ga.topk = b.topk;
         ga.n_docs = ix->n_docs;
         const bool prof = g_prof.load() != 0;
-        if (prof) {
+        const bool timed = prof || b.time_gather;
+        if (timed) {
             for (hipEvent_t &e : ws.ev)
                 if (!e) COBS_HIP(hipEventCreate(&e));
             COBS_HIP(hipEventRecord(ws.ev[0], st));
         }
-        if (n_slices) COBS_HIP(launch_gather(ga, planes, grid, st));
-        if (prof) COBS_HIP(hipEventRecord(ws.ev[1], st));
+        if (n_slices) COBS_HIP(launch_gather(ga, planes, unroll, grid, st));
+        if (timed) COBS_HIP(hipEventRecord(ws.ev[1], st));
         auto account = [&](const uint32_t *nt) -> cobs_status {
-            if (!prof) return COBS_OK;
+            if (!timed) return COBS_OK;
             float ms = 0.f;
             COBS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]));
+            out.gather_ms = ms;
+            if (!prof) return COBS_OK;
             uint64_t terms = 0, per_term = 0;
             for (uint32_t i = 0; i < n; ++i) terms += nt[i];
             for (const SliceDesc &sd : ix->slices) per_term += sd.width;
@@ -1000,6 +1005,56 @@ cobs_status cobs_query_terms(const cobs_index *cix, const uint8_t *bytes, const 
     release_workspace(ix, ws);
     if (s == COBS_OK && num_terms) std::memcpy(num_terms, bo.num_terms.data(), (size_t)n_queries * 4);
     return s;
+}
+
+cobs_status cobs_set_tuning(cobs_index *ix, const cobs_tuning *t)
+{
+    if (!ix || !t) return set_error(COBS_EINVAL, "NULL argument");
+    if (t->unroll && !gather_unroll_valid((int)t->unroll, (int)ix->prm.num_hashes))
+        return set_error(COBS_EINVAL, "unsupported unroll for this index");
+    ix->tuned_unroll = (int)t->unroll;
+    ix->tuned_chunk = t->chunk;
+    return COBS_OK;
+}
+
+cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
+                      uint32_t n_queries, uint32_t mem, void *stream, cobs_tuning *best)
+{
+    if (!ix || !best) return set_error(COBS_EINVAL, "NULL argument");
+    const int h = (int)ix->prm.num_hashes;
+    const int unrolls[2] = {h == 1 ? 4 : 2, h == 1 ? 8 : 4};
+    const uint32_t chunks[6] = {0, 256, 512, 1024, 2048, 4096};
+    Workspace *ws = acquire_workspace(ix);
+    cobs_tuning win{0, 0, 1e300};
+    cobs_status s = COBS_OK;
+    for (int u : unrolls) {
+        for (uint32_t c : chunks) {
+            BatchSpec spec;
+            spec.bytes = bytes;
+            spec.q_off = q_off;
+            spec.n = n_queries;
+            spec.mem = mem;
+            spec.k_num = 1;
+            spec.k_den = 1;
+            spec.unroll = (uint32_t)u;
+            spec.chunk = c;
+            spec.time_gather = true;
+            double t = 1e300;
+            for (int rep = 0; rep < 2 && s == COBS_OK; ++rep) {   // first run warms up
+                BatchOut bo;
+                s = run_batch(ix, *ws, spec, (hipStream_t)stream, bo);
+                if (rep) t = bo.gather_ms;
+            }
+            if (s != COBS_OK) break;
+            if (t < win.gather_ms) win = cobs_tuning{(uint32_t)u, c, t};
+        }
+    }
+    release_workspace(ix, ws);
+    if (s != COBS_OK) return s;
+    ix->tuned_unroll = (int)win.unroll;
+    ix->tuned_chunk = win.chunk;
+    *best = win;
+    return COBS_OK;
 }
 
 cobs_status cobs_profile(int enable)

@@ -74,6 +74,7 @@ struct BatchOut {
     std::vector<uint32_t> start;       // first hit per query
     const uint32_t *ids = nullptr;     // pinned, valid until the next batch
     const uint32_t *scores = nullptr;
+    double gather_ms = 0;              // when BatchSpec::time_gather
 };
 
 struct BatchSpec {
@@ -82,9 +83,11 @@ struct BatchSpec {
     uint32_t n = 0;
     uint32_t mem = COBS_MEM_HOST;
     uint32_t k_num = 0, k_den = 1, topk = 0, score_bits = 32;
-    uint32_t chunk = 0;                // 0 = automatic
+    uint32_t chunk = 0;                // terms per work item; 0 = tuned or automatic
+    uint32_t unroll = 0;               // terms in flight per wavefront; 0 = tuned or default
     uint32_t *full_scores = nullptr;   // host [n * n_docs]: full score mode
     uint64_t *terms_out = nullptr;     // host [windows]: terms-only mode
+    bool time_gather = false;          // HIP events around the gather launch
 };
 
 }  // namespace cobs
@@ -102,6 +105,8 @@ struct cobs_index {
     uint32_t *d_order = nullptr;
     cobs::SliceDesc *d_slices = nullptr;
     cobs::Seeds seeds{};
+    int tuned_unroll = 0;              // set by cobs_tune (0 = default)
+    uint32_t tuned_chunk = 0;          // set by cobs_tune (0 = automatic)
     std::mutex pool_mu;
     std::vector<cobs::Workspace *> pool;
     ~cobs_index();

@@ -248,6 +248,35 @@ def test_long_query_multi_chunk_and_global_table():
     check_queries(gix, oix, data, off, k=(0, 1), topk=7, mode=1)
 
 
+@pytest.mark.parametrize("unroll,chunk", [(4, 32), (8, 100), (4, 1024), (8, 7)])
+def test_launch_shapes_give_identical_results(workload, unroll, chunk):
+    # every instantiated unroll and several term-chunk sizes (many partial
+    # merges at chunk 7) give the oracle's scores and hits
+    w, d, qs, gix, oix = workload
+    if w.h > 1:
+        unroll //= 2
+    gix.set_tuning(unroll, chunk)
+    try:
+        sc, l = gix.scores(qs.bytes, qs.q_off)
+        for i in range(qs.n):
+            want, wl = oix.query_scores(qs.get(i))
+            assert l[i] == wl and np.array_equal(sc[i], want), (unroll, chunk, i)
+        check_queries(gix, oix, qs.bytes, qs.q_off, k=(1, 2), topk=4, mode=0)
+    finally:
+        gix.set_tuning(0, 0)
+
+
+def test_autotune_keeps_results(workload):
+    w, d, qs, gix, oix = workload
+    before = gix.query(qs.bytes, qs.q_off, k=(1, 2))
+    t = gix.tune(qs.bytes, qs.q_off)
+    assert t["gather_ms"] > 0 and t["unroll"] in ((4, 8) if w.h == 1 else (2, 4))
+    after = gix.query(qs.bytes, qs.q_off, k=(1, 2))
+    for x, y in zip(before, after):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+    gix.set_tuning(0, 0)
+
+
 def test_hits_and_flat_results_agree(workload):
     # cobs_query_batch (one cobs_hits per query) and cobs_query_results (flat)
     w, d, qs, gix, oix = workload
