@@ -89,6 +89,32 @@ def build_index_dna(cobs, synth, torch, w, chunk_bytes):
     return ix
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gather_compact100k_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1905_09624_amd", "csrc", "kernels.hip")
+
+
+def committed_traffic(workload: str):
+    """HBM bytes per gather launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
+    the kernel source changed since the counters were taken or the summary
+    covers another workload."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernels.hip sha256") != src or fields.get("workload") != workload:
+        return None
+    try:
+        return int(fields["HBM bytes per gather launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, synth, oracle, qs, budget_s):
     """The CPU oracle on a bounded sample: documents 0..S-1 of the workload
     (their own compact plan), the first queries of the set; lookups/s scaled
@@ -266,7 +292,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": committed_traffic(w.name),
         },
         "gather_kernel_ms": gather_ms,
         "tuning": tuning,

@@ -630,7 +630,11 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     int unroll = b.unroll ? (int)b.unroll : (ix->tuned_unroll ? ix->tuned_unroll : gather_default_unroll((int)h));
     if (!gather_unroll_valid(unroll, (int)h)) unroll = gather_default_unroll((int)h);
     const int grid = gather_grid(planes, unroll, (int)h);
-    const uint32_t C = b.chunk ? b.chunk : (ix->tuned_chunk ? ix->tuned_chunk : auto_chunk(W, n, n_slices, grid));
+    // a tuned chunk applies to batches that fill the persistent grid with one
+    // item per (query, slice); smaller batches split their queries instead
+    const bool fills = (uint64_t)n * n_slices >= 2ull * (uint64_t)grid * 4;
+    const uint32_t C = b.chunk ? b.chunk
+                               : (ix->tuned_chunk && fills ? ix->tuned_chunk : auto_chunk(W, n, n_slices, grid));
     uint64_t pslots = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t nw = wbase[i + 1] - wbase[i];
