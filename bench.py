@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk-gb", type=float, default=8.0,
                     help="device bytes of documents generated per build run")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="'unroll,chunk' launch shape instead of autotuning")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -204,12 +206,17 @@ def main():
         del src, dst
 
     # autotune the gather launch shape on a separate query set of the same shape
-    if w.kind == "dna":
-        tq = synth.dna_queries(w, n=qs.n, first=qs.n)
+    if args.tuning:
+        u, c = (int(x) for x in args.tuning.split(","))
+        ix.set_tuning(u, c)
+        tuning = {"unroll": u, "chunk": c, "gather_ms": None}
     else:
-        tq = synth.text_queries(w, d, n=qs.n)
-    tuning = ix.tune(torch.from_numpy(tq.bytes.copy()).to("cuda"), tq.q_off)
-    log(f"tuned: {tuning}")
+        if w.kind == "dna":
+            tq = synth.dna_queries(w, n=qs.n, first=qs.n)
+        else:
+            tq = synth.text_queries(w, d, n=qs.n)
+        tuning = ix.tune(torch.from_numpy(tq.bytes.copy()).to("cuda"), tq.q_off)
+    log(f"tuning: {tuning}")
 
     qdev = torch.from_numpy(qs.bytes.copy()).to("cuda")     # resident in HBM
     q_off = qs.q_off
