@@ -49,6 +49,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk-gb", type=float, default=8.0,
                     help="device bytes of documents generated per build run")
+    ap.add_argument("--serve-rates", type=str, default="1000,7100",
+                    help="Poisson arrival rates (q/s) of the serving measurement; '' skips it")
+    ap.add_argument("--serve-pool", type=int, default=1000)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-max", type=int, default=8000)
     ap.add_argument("--tuning", type=str, default="",
                     help="'unroll,chunk' launch shape instead of autotuning")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
@@ -115,6 +120,60 @@ def committed_traffic(workload: str):
         return int(fields["HBM bytes per gather launch"])
     except (KeyError, ValueError):
         return None
+
+
+def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, plain_n):
+    """Served latency and throughput on the resident index: Poisson arrivals at
+    each rate (open loop, native submitter), query lengths log-uniform in
+    [31, 10^6] bp, half planted; beside it the plain path (one query per
+    launch, back to back) and one batch of the whole pool."""
+    import numpy as np
+    w5 = synth.CONFIGS[5]
+    t0 = time.time()
+    pool = synth.dna_queries(w5, n=pool_n)
+    log(f"serving pool: {pool_n} queries, {pool.bytes.size / 1e6:.1f} MB ({time.time() - t0:.1f}s)")
+    k = w5.k
+    out = {"workload": "serve-100k: compact-100k index resident, queries log-uniform "
+                       "[31, 1e6] bp, 50% planted, Poisson arrivals", "rates": []}
+    # plain path: closed loop, one query per launch
+    sub = pool.subset(range(min(plain_n, pool_n)))
+    lat = []
+    nt_total = 0
+    for i in range(sub.n):
+        q = np.frombuffer(sub.get(i), np.uint8)
+        off = np.array([0, q.size], np.uint64)
+        t1 = time.perf_counter()
+        nt = ix.query_flat(q, off, k=k, mode=cobs.MODE_PLAIN)[0]
+        lat.append(time.perf_counter() - t1)
+        nt_total += int(nt.sum())
+    lat = np.array(lat)
+    plain = {"queries_per_s": sub.n / lat.sum(), "lookups_per_s": nt_total / lat.sum(),
+             "p50_ms": float(np.percentile(lat, 50) * 1e3),
+             "p99_ms": float(np.percentile(lat, 99) * 1e3), "queries": sub.n}
+    out["plain_path"] = plain
+    log(f"serving plain path: {plain}")
+    # the whole pool as one batch (host bytes, as the server receives them)
+    t1 = time.perf_counter()
+    nt = ix.query_flat(pool.bytes, pool.q_off, k=k)[0]
+    bt = time.perf_counter() - t1
+    out["one_batch"] = {"queries_per_s": pool_n / bt, "lookups_per_s": float(nt.sum()) / bt,
+                        "seconds": bt}
+    for rate in rates:
+        n = int(min(max_req, max(rate * per_rate_s, 200)))
+        idx = np.arange(n) % pool_n
+        q = pool.subset(idx) if n != pool_n else pool
+        arr = synth.arrivals(0x5E7E + int(rate), n, float(rate))
+        srv = cobs.Server(ix, num_streams=4)
+        lat_ns, nh = srv.replay(q.bytes, q.q_off, arr, k=k)
+        st = srv.stop()
+        rec = {"rate_qps": rate, "requests": n, "completed": int(st["completed"]),
+               "batches": int(st["batches"]), "p50_ms": st["p50_ns"] / 1e6,
+               "p99_ms": st["p99_ns"] / 1e6, "max_ms": st["max_ns"] / 1e6,
+               "queries_per_s": st["queries_per_s"], "lookups_per_s": st["lookups_per_s"],
+               "vs_plain_throughput": st["queries_per_s"] / plain["queries_per_s"]}
+        out["rates"].append(rec)
+        log(f"serving at {rate} q/s: {rec}")
+    return out
 
 
 def cpu_baseline(w, synth, oracle, qs, budget_s):
@@ -270,6 +329,12 @@ def main():
     plain_rate = int(pnt.sum()) / plain_dt
     log(f"plain path: {npq} queries in {plain_dt:.3f}s")
 
+    serving = None
+    if args.serve_rates and args.config == 3:
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        serving = serve_measure(cobs, synth, torch, ix, rates, args.serve_pool,
+                                args.serve_seconds, args.serve_max, 100)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -309,6 +374,7 @@ def main():
         "plain_path": {"value": plain_rate, "unit": "lookups/s", "queries": npq,
                        "speedup_batched": value / plain_rate if plain_rate else None},
         "build_s": build_s,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -145,11 +145,15 @@ uint64_t synth_dna_query(uint64_t seed, uint32_t i, int len_kind, double a, doub
     if (!out) return L;
     if (s >= 0) {
         synth_doc_bases(seed, (uint32_t)s, offset, L, out);
+        /* one draw per 4 bases: 16-bit fraction for the substitution test,
+         * 16 bits for the choice among the 3 other bases */
+        const uint32_t cut = (uint32_t)(subst * 65536.0 + 0.5);
         for (uint64_t j = 0; j < L; ++j) {
-            draw(seed, ST_Q_SUBST, j, i, o);
-            if ((double)o[0] * (1.0 / 4294967296.0) < subst) {
+            if ((j & 3) == 0) draw(seed, ST_Q_SUBST, j >> 2, i, o);
+            const uint32_t wv = o[j & 3];
+            if ((wv & 0xFFFFu) < cut) {
                 int c = out[j] == 'A' ? 0 : out[j] == 'C' ? 1 : out[j] == 'G' ? 2 : 3;
-                int r = (int)(((uint64_t)o[1] * 3u) >> 32);  /* 0..2 */
+                int r = (int)(((wv >> 16) * 3u) >> 16);  /* 0..2 */
                 out[j] = (uint8_t)ACGT[(c + 1 + r) & 3];
             }
         }
