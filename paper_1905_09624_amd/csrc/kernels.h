@@ -12,6 +12,7 @@ constexpr uint64_t kInvalidTerm = ~0ull;   // DNA window with a non-ACGT byte
 constexpr uint32_t kSliceBytes = 1024;     // one wavefront: 64 lanes x 16 bytes
 constexpr uint32_t kLdsTableSlots = 8192;  // dedup table held in LDS (64 KiB)
 constexpr uint32_t kSortRun = 2048;        // candidates sorted in LDS per run
+constexpr uint32_t kSliceDocs = 8192;      // documents per slice (score buffer stride)
 
 struct Seeds {
     uint64_t s[kMaxHashes];
@@ -40,7 +41,7 @@ struct QInfo {
     uint64_t hbase;    // first unique term of the query in the term arrays
     uint32_t ell;      // distinct terms
     uint32_t nch;      // term chunks
-    uint32_t pbase;    // first partial slot (multi-chunk queries)
+    uint32_t pbase;    // score-buffer slot (queries split into several chunks)
     uint32_t thr;      // T = ceil(k_num * ell / k_den); > ell means none
 };
 
@@ -71,7 +72,7 @@ struct GatherArgs {
     const uint64_t *total_items;       // device scalar
     unsigned long long *work_counter;  // device scalar
     uint32_t *tickets;                 // [n_queries * n_slices]
-    uint32_t *partials;
+    uint32_t *accum;                   // score buffers of split queries (zero between launches)
     unsigned long long *cand_counter;  // device scalar
     uint64_t *cand_key;                // (score << 32) | ~input_id
     uint32_t *cand_q;

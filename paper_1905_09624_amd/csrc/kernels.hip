@@ -219,7 +219,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, cons
         const uint32_t ell = nterms[q];
         const uint32_t nch = ell ? (ell + chunk - 1) / chunk : 0;
         sc += nch;
-        sp += nch > 1 ? nch : 0;
+        sp += nch > 1 ? 1u : 0u;
     }
     s_ch[tid] = sc;
     s_ps[tid] = sp;
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, cons
         chunk_prefix[q] = cbase;
         qcount[q] = 0;
         cbase += nch;
-        pbase += nch > 1 ? nch : 0;
+        pbase += nch > 1 ? 1u : 0u;
         bad |= (uint64_t)ell > ell_limit;
     }
     if (bad) atomicOr(flags, 1u);
@@ -331,30 +331,6 @@ struct Counter {
                 csa(H[2][d], e, H[2][d], u0, u1);
                 ripple(d, 3, e);
             }
-        }
-    }
-
-    // add another P-plane counter stored plane-major (64 lanes x 16 B per
-    // plane); at most 4 of its planes are held in registers at a time, so the
-    // merge does not raise the kernel's register count
-    __device__ __forceinline__ void add_planes(const uint4 *y)
-    {
-        uint32_t c[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int p0 = 0; p0 < P; p0 += 4) {
-            uint4 v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (p0 + k < P) v[k] = y[(p0 + k) * 64];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (p0 + k < P) {
-                    const uint32_t yv[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) csa(H[p0 + k][d], c[d], H[p0 + k][d], yv[d], c[d]);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
         }
     }
 
@@ -458,14 +434,24 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
             }
         }
 
-        // several chunks of one (query, slice): the last to finish merges
+        // Several chunks of one (query, slice): each adds its counts into the
+        // query's score buffer (device-scope atomics; document (lane, d, bit)
+        // at (d*32 + bit)*64 + lane, so one instruction's 64 lanes touch 256
+        // consecutive bytes); the last chunk to finish reads the totals back
+        // into bit planes and clears the buffer for the next batch.  The cost
+        // of the merge does not grow with the number of chunks.
         if (qn.nch > 1) {
-            const uint64_t plane_words = (uint64_t)P * 256;
-            uint4 *mine = (uint4 *)(a.partials +
-                                    ((uint64_t)(qn.pbase + chunk) * a.n_slices + sl) * plane_words);
+            uint32_t *acc = a.accum + ((uint64_t)qn.pbase * a.n_slices + sl) * kSliceDocs;
 #pragma unroll
-            for (int p = 0; p < P; ++p)
-                mine[p * 64 + lane] = make_uint4(cnt.H[p][0], cnt.H[p][1], cnt.H[p][2], cnt.H[p][3]);
+            for (int d = 0; d < 4; ++d) {
+#pragma unroll 4
+                for (int bit = 0; bit < 32; ++bit) {
+                    const uint32_t c = cnt.score(d, bit);
+                    if (c)
+                        __hip_atomic_fetch_add(acc + (d * 32 + bit) * 64 + lane, c, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
             __threadfence();
             uint32_t tk = 0;
             if (lane == 0) tk = atomicAdd(&a.tickets[(uint64_t)qi * a.n_slices + sl], 1u);
@@ -473,14 +459,17 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
             if (tk != qn.nch - 1) continue;
             __threadfence();
             if (lane == 0) a.tickets[(uint64_t)qi * a.n_slices + sl] = 0;   // ready for reuse
-            // sum every chunk's partial, this wavefront's own included, into a
-            // cleared counter (merging into the live one makes the compiler
-            // keep a second copy of the planes)
             cnt.clear();
-            for (uint32_t c2 = 0; c2 < qn.nch; ++c2) {
-                const uint4 *other = (const uint4 *)(a.partials +
-                                     ((uint64_t)(qn.pbase + c2) * a.n_slices + sl) * plane_words);
-                cnt.add_planes(other + lane);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+#pragma unroll 4
+                for (int bit = 0; bit < 32; ++bit) {
+                    uint32_t *cell = acc + (d * 32 + bit) * 64 + lane;
+                    const uint32_t c = __hip_atomic_load(cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    *cell = 0;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) cnt.H[p][d] |= ((c >> p) & 1u) << bit;
+                }
             }
         }
 

@@ -638,7 +638,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     uint64_t pslots = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t nw = wbase[i + 1] - wbase[i];
-        if (nw > C) pslots += (nw + C - 1) / C;
+        if (nw > C) pslots += 1;   // may be split: one score buffer
     }
     const TermSpec ts = term_spec(ix->prm);
 
@@ -694,7 +694,13 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     COBS_HIP(ws.qinfo.ensure((size_t)n * sizeof(QInfo)));
     COBS_HIP(ws.chunk_prefix.ensure((size_t)(n + 1) * 4));
     COBS_HIP(ws.scalars.ensure(sizeof(Scalars)));
-    COBS_HIP(ws.partials.ensure(std::max<uint64_t>(pslots * n_slices * (uint64_t)planes * 1024, 256)));
+    // score buffers of split queries: zero on allocation, left zero by every
+    // complete gather launch
+    const uint64_t accum_words = pslots * n_slices * (uint64_t)kSliceDocs;
+    if (ws.accum_words < accum_words || !ws.accum.p) {
+        COBS_HIP(ws.accum.ensure(std::max<uint64_t>(accum_words, 64) * 4, true, st));
+        ws.accum_words = ws.accum.cap / 4;
+    }
     COBS_HIP(ws.qcount.ensure((size_t)n * 4));
     COBS_HIP(hipMemsetAsync(ws.scalars.p, 0, sizeof(Scalars), st));
     const uint64_t ell_limit = b.score_bits == 16 ? 0xFFFFull : 0xFFFFFFFFull;
@@ -723,7 +729,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         ga.total_items = &dsc->total_items;
         ga.work_counter = &dsc->work_counter;
         ga.tickets = ws.tickets.as<uint32_t>();
-        ga.partials = ws.partials.as<uint32_t>();
+        ga.accum = ws.accum.as<uint32_t>();
         ga.cand_counter = &dsc->cand_counter;
         ga.cand_key = ws.cand_key.as<uint64_t>();
         ga.cand_q = ws.cand_q.as<uint32_t>();

@@ -57,11 +57,12 @@ struct Block {
 // Everything one query batch needs on the device; reused across batches.
 struct Workspace {
     DevBuf bytes, qstart, wbase, terms, uterms, hashes, nterms, table, tbase;
-    DevBuf tickets, qinfo, chunk_prefix, scalars, partials;
+    DevBuf tickets, qinfo, chunk_prefix, scalars, accum;
     DevBuf cand_key, cand_q, qcount, gstart, gcursor, seg_a, seg_b;
     DevBuf out_start, out_n, out_id, out_score, full;
     HostBuf h_stage, h_small, h_out;
     uint64_t tickets_slots = 0;
+    uint64_t accum_words = 0;
     uint64_t cand_cap = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};   // gather timing (cobs_profile)
     ~Workspace();
