@@ -138,6 +138,10 @@ typedef struct {
     uint32_t n_blocks;
     cobs_params params;
     uint64_t total_bytes;   /* device bytes of the signature matrix */
+    uint64_t score_bytes;   /* device bytes of one query's score buffer: 4 per
+                               document, each 8192-document slice rounded up
+                               to whole 128-document lanes (the unit by which
+                               cobs_serve admits requests) */
 } cobs_index_info_t;
 
 cobs_status cobs_index_info(const cobs_index *ix, cobs_index_info_t *info);
@@ -240,15 +244,21 @@ void cobs_results_free(cobs_results *r);
 /* ---- serving ------------------------------------------------------------ */
 
 /*
- * Continuous-batching server over a resident index.  Requests are admitted
- * while the score memory they reserve (n_docs * 4 bytes each) fits
- * score_budget_bytes and a batch slot is free; admitted requests are grouped
- * into device batches, and up to num_streams batches run on the GPU at once,
- * so requests arriving while others run join the next batch.
- *  score_budget_bytes  0 = 1/4 of the free device memory at start
+ * Continuous-batching server over a resident index.  The server allocates
+ * score_budget_bytes of device memory at start as a pool of per-query score
+ * buffers (score_bytes of cobs_index_info_t each); a request is admitted, in
+ * arrival order, when a buffer is free and holds it until its result is
+ * ready.  Admitted requests are grouped into device batches, and up to
+ * num_streams batches run on the GPU at once, so requests arriving while
+ * others run join the next batch.  Each stream's workspace is sized at start
+ * for max_batch_queries queries of max_batch_terms windows in total, so a
+ * batch within those limits allocates nothing.
+ *  score_budget_bytes  0 = 4096 score buffers, at most 1/4 of the free
+ *                      device memory at start
  *  num_streams         concurrent batches in flight (1..8), 0 = 2
  *  max_batch_queries   0 = 4096
- *  max_batch_terms     windows per batch before it is cut, 0 = 2^25
+ *  max_batch_terms     windows per batch before it is cut, 0 = 2^23 (a
+ *                      longer request still runs, as a batch of its own)
  *  score_bits          16 or 32 (0 = 32)
  */
 typedef struct {
@@ -271,7 +281,7 @@ cobs_status cobs_serve(cobs_index *ix, const cobs_serve_opts *opts, cobs_server 
 /*
  * Submit one query (host bytes, copied).  arrival_ns is the request's arrival
  * on the CLOCK_MONOTONIC clock (0 = now); latency counts from it.  Returns
- * EBUDGET when the request alone exceeds the budget.
+ * EBUDGET when the budget holds no score buffer at all.
  */
 cobs_status cobs_submit(cobs_server *s, const uint8_t *query, uint64_t len,
                         uint32_t k_num, uint32_t k_den, uint32_t topk,
@@ -310,8 +320,11 @@ typedef struct {
     double gather_ms;    /* cobs_tune: the chosen shape's gather time */
 } cobs_tuning;
 
-/* Time the gather kernel on the sample batch for every supported
- * (unroll, chunk) pair, keep the fastest for this index, report it in *best.
+/* Time the gather kernel on the sample batch for every supported unroll and
+ * chunk in {automatic, 512, 1024, 2048, 4096, 8192, 16384, 2^20}, keep the
+ * fastest pair for this index, report it in *best.  A tuned chunk applies to
+ * batches with at least two work items per resident wavefront; smaller
+ * batches keep the automatic split, which spreads long queries over the GPU.
  * The sample should resemble the batches to come (a separate query set). */
 cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
                       uint32_t n_queries, uint32_t mem, void *stream, cobs_tuning *best);

@@ -43,7 +43,7 @@ class DocsC(C.Structure):
 
 class IndexInfo(C.Structure):
     _fields_ = [("n_docs", C.c_uint32), ("n_blocks", C.c_uint32), ("params", Params),
-                ("total_bytes", C.c_uint64)]
+                ("total_bytes", C.c_uint64), ("score_bytes", C.c_uint64)]
 
 
 class QueryOpts(C.Structure):
@@ -237,7 +237,8 @@ class Index:
     def info(self) -> dict:
         i = IndexInfo()
         _check(lib().cobs_index_info(self._h, C.byref(i)))
-        return dict(n_docs=i.n_docs, n_blocks=i.n_blocks, total_bytes=i.total_bytes)
+        return dict(n_docs=i.n_docs, n_blocks=i.n_blocks, total_bytes=i.total_bytes,
+                    score_bytes=i.score_bytes)
 
     def block(self, b: int) -> dict:
         f, d = C.c_uint32(), C.c_uint32()

@@ -13,6 +13,7 @@ constexpr uint32_t kSliceBytes = 1024;     // one wavefront: 64 lanes x 16 bytes
 constexpr uint32_t kLdsTableSlots = 8192;  // dedup table held in LDS (64 KiB)
 constexpr uint32_t kSortRun = 2048;        // candidates sorted in LDS per run
 constexpr uint32_t kSliceDocs = 8192;      // documents per slice (score buffer stride)
+constexpr uint32_t kDedupWindowsPerGroup = 8192;  // windows per workgroup of a global-table query
 
 struct Seeds {
     uint64_t s[kMaxHashes];
@@ -34,7 +35,14 @@ struct SliceDesc {
     uint32_t ndocs;    // documents in the slice
     uint32_t doc0;     // sorted position of the slice's first document
     uint32_t block;
+    uint32_t acc_off;  // first word of the slice in a query's score buffer
+    uint32_t lanes;    // lanes holding documents: ceil(ndocs / 128)
 };
+
+// Score buffer of one query (split queries only): for each slice, 128 * lanes
+// words, document (lane, d, bit) of the slice at acc_off + (d*32 + bit)*lanes
+// + lane; n_docs + 127 * n_slices words at most.
+uint64_t score_buffer_words(const SliceDesc *slices, uint32_t n_slices);
 
 // Per-query state filled by the plan kernel.
 struct QInfo {
@@ -73,6 +81,7 @@ struct GatherArgs {
     unsigned long long *work_counter;  // device scalar
     uint32_t *tickets;                 // [n_queries * n_slices]
     uint32_t *accum;                   // score buffers of split queries (zero between launches)
+    uint64_t acc_words;                // words per score buffer
     unsigned long long *cand_counter;  // device scalar
     uint64_t *cand_key;                // (score << 32) | ~input_id
     uint32_t *cand_q;
@@ -86,24 +95,34 @@ struct GatherArgs {
 
 // a1: one term per window of every query (kInvalidTerm for DNA windows with
 // a non-ACGT byte).  qstart[i]: first byte of query i; wbase[i]: first window.
+// Also zeroes nterms[0, n_queries).
 hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const uint64_t *wbase,
                           uint32_t n_queries, uint64_t total_windows, TermSpec ts,
-                          uint64_t *terms, hipStream_t st);
+                          uint64_t *terms, uint32_t *nterms, hipStream_t st);
 
-// a2+a3: per-query set of terms (hash-set dedup, LDS or global table) and the
-// h hashes of each distinct term.  tbase[i]: the query's global table (used
-// when its table does not fit kLdsTableSlots).
+// a2+a3: per-query set of terms (hash-set dedup) and the h hashes of each
+// distinct term; nterms[i] = l of query i (zeroed by launch_extract).  A query
+// whose set fits kLdsTableSlots is one workgroup with an LDS table; a larger
+// one has dedup_table_slots(windows) global slots at table + tbase[i] (cleared
+// here) and dedup_groups(windows) workgroups.  bprefix[i]: first workgroup of
+// query i, n_groups = bprefix[n_queries]; table_slots: total global slots.
 hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint64_t *tbase,
-                        uint64_t *table, uint64_t *uterms, uint64_t *hashes, uint32_t *nterms,
-                        uint32_t n_queries, TermSpec ts, Seeds seeds, hipStream_t st);
-uint64_t dedup_table_cap(uint64_t windows);   // slots of a query's table
+                        const uint32_t *bprefix, uint32_t n_groups, uint64_t *table,
+                        uint64_t table_slots, uint64_t *uterms, uint64_t *hashes,
+                        uint32_t *nterms, uint32_t n_queries, TermSpec ts, Seeds seeds,
+                        hipStream_t st);
+uint64_t dedup_table_cap(uint64_t windows);    // hash-set capacity for a query (power of 2)
+uint64_t dedup_table_slots(uint64_t windows);  // global slots (0: LDS table)
+uint32_t dedup_groups(uint64_t windows);       // workgroups of the query
 // tickets: [n_queries * n_slices], zero before the first gather; every
 // complete gather launch leaves them zero again.
 
-// Per-query chunks, thresholds, partial slots, work totals; zeroes counters.
-hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, uint32_t n_queries,
-                       uint32_t chunk, uint32_t n_slices, uint32_t k_num, uint32_t k_den,
-                       uint64_t ell_limit, QInfo *qinfo, uint32_t *chunk_prefix,
+// Per-query chunks, thresholds, score-buffer slots, work totals; zeroes
+// counters.  A query split into several chunks uses score buffer slot[i] when
+// slot is non-NULL, else the next free one in query order.
+hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, const uint32_t *slot,
+                       uint32_t n_queries, uint32_t chunk, uint32_t n_slices, uint32_t k_num,
+                       uint32_t k_den, uint64_t ell_limit, QInfo *qinfo, uint32_t *chunk_prefix,
                        uint64_t *total_items, unsigned long long *work_counter,
                        unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags,
                        hipStream_t st);

@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace cobs {
 namespace {
 
@@ -126,9 +128,11 @@ __host__ __device__ __forceinline__ uint64_t table_cap(uint64_t n)
 
 __global__ void extract_kernel(const uint8_t *bytes, const uint64_t *qstart,
                                const uint64_t *wbase, uint32_t n, uint64_t W, TermSpec ts,
-                               uint64_t *terms)
+                               uint64_t *terms, uint32_t *nterms)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        nterms[i] = 0;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < W; w += stride) {
         const uint32_t qi = bsearch_le(wbase, n, w);
         bool ok;
@@ -139,11 +143,11 @@ __global__ void extract_kernel(const uint8_t *bytes, const uint64_t *qstart,
 
 // ---- a2 + a3: per-query term set and hashes ----------------------------------------
 
-template <bool kLds>
-__device__ __forceinline__ bool set_insert(uint64_t *table, uint64_t cap, uint64_t t,
-                                           uint64_t slot, uint32_t *empty_flag)
+// Insert t (!= kEmpty, which marks free slots) into an open-addressing set,
+// linear probing from slot; true when t was not there yet.  Callers record the
+// term kEmpty itself in a flag word.
+__device__ __forceinline__ bool set_insert(uint64_t *table, uint64_t cap, uint64_t t, uint64_t slot)
 {
-    if (t == kEmpty) return atomicOr(empty_flag, 1u) == 0;
     for (;;) {
         const unsigned long long old =
             atomicCAS((unsigned long long *)&table[slot], (unsigned long long)kEmpty,
@@ -154,55 +158,81 @@ __device__ __forceinline__ bool set_insert(uint64_t *table, uint64_t cap, uint64
     }
 }
 
-template <bool kLds>
-__device__ void dedup_body(uint64_t *table, uint64_t cap, const uint64_t *terms, uint64_t w0,
-                           uint64_t nw, uint64_t *uterms, uint64_t *hashes, TermSpec ts,
-                           const Seeds &seeds, uint32_t *lcount, uint32_t *lflag)
+// Windows [b, e) of one query: insert every valid term; each wavefront
+// reserves output positions for its new terms with one atomic add on count.
+__device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint64_t *flag,
+                                            const uint64_t *terms, uint64_t w0, uint64_t b,
+                                            uint64_t e, uint64_t *uterms, uint64_t *hashes,
+                                            TermSpec ts, const Seeds &seeds, uint32_t *count)
 {
-    for (uint64_t s = threadIdx.x; s < cap; s += blockDim.x) table[s] = kEmpty;
-    __syncthreads();
-    for (uint64_t w = threadIdx.x; w < nw; w += blockDim.x) {
-        const uint64_t t = terms[w0 + w];
-        if (ts.kind == 0 && t == kInvalidTerm) continue;
-        uint64_t hs[kMaxHashes];
+    const uint32_t lane = lane_id();
+    for (uint64_t base = b; base < e; base += blockDim.x) {
+        const uint64_t w = base + threadIdx.x;
+        bool fresh = false;
+        uint64_t t = 0, hs[kMaxHashes];
+        if (w < e) {
+            t = terms[w0 + w];
+            if (ts.kind == 1 || t != kInvalidTerm) {
 #pragma unroll
-        for (int i = 0; i < kMaxHashes; ++i)
-            if (i < (int)ts.h) hs[i] = mix64(t ^ seeds.s[i]);
-        if (set_insert<kLds>(table, cap, t, hs[0] & (cap - 1), lflag)) {
-            const uint32_t pos = atomicAdd(lcount, 1u);
-            uterms[w0 + pos] = t;
+                for (int i = 0; i < kMaxHashes; ++i)
+                    if (i < (int)ts.h) hs[i] = mix64(t ^ seeds.s[i]);
+                fresh = t == kEmpty ? atomicCAS((unsigned long long *)flag,
+                                                (unsigned long long)kEmpty, 0ull) == kEmpty
+                                    : set_insert(table, cap, t, hs[0] & (cap - 1));
+            }
+        }
+        const uint64_t m = __ballot(fresh);
+        if (m == 0) continue;
+        uint32_t pos0 = 0;
+        if (lane == (uint32_t)__builtin_ctzll(m)) pos0 = atomicAdd(count, (uint32_t)__popcll(m));
+        pos0 = lane_u32(pos0, (uint32_t)__builtin_ctzll(m));
+        if (fresh) {
+            const uint64_t pos = w0 + pos0 + __popcll(m & ((1ull << lane) - 1ull));
+            uterms[pos] = t;
 #pragma unroll
             for (int i = 0; i < kMaxHashes; ++i)
-                if (i < (int)ts.h) hashes[(w0 + pos) * ts.h + i] = hs[i];
+                if (i < (int)ts.h) hashes[pos * ts.h + i] = hs[i];
         }
     }
 }
 
+// One workgroup per query whose set fits in LDS; queries with a global table
+// (cleared to kEmpty beforehand, cap slots plus one flag word) are spread over
+// several workgroups, which count into nterms (zeroed by the extract kernel).
+// bprefix[i]: first workgroup of query i.
 __global__ __launch_bounds__(256) void dedup_kernel(const uint64_t *terms, const uint64_t *wbase,
-                                                    const uint64_t *tbase, uint64_t *gtable,
-                                                    uint64_t *uterms, uint64_t *hashes,
-                                                    uint32_t *nterms, TermSpec ts, Seeds seeds)
+                                                    const uint64_t *tbase, const uint32_t *bprefix,
+                                                    uint32_t n, uint64_t *gtable, uint64_t *uterms,
+                                                    uint64_t *hashes, uint32_t *nterms, TermSpec ts,
+                                                    Seeds seeds)
 {
     __shared__ uint64_t ltable[kLdsTableSlots];
-    __shared__ uint32_t lcount, lflag;
-    const uint32_t qi = blockIdx.x;
+    __shared__ uint64_t lflag;
+    __shared__ uint32_t lcount;
+    const uint32_t qi = bsearch_le(bprefix, n, blockIdx.x);
+    const uint32_t part = blockIdx.x - bprefix[qi];
     const uint64_t w0 = wbase[qi], nw = wbase[qi + 1] - w0;
-    if (threadIdx.x == 0) { lcount = 0; lflag = 0; }
-    __syncthreads();
     const uint64_t cap = table_cap(nw);
-    if (cap <= kLdsTableSlots)
-        dedup_body<true>(ltable, cap, terms, w0, nw, uterms, hashes, ts, seeds, &lcount, &lflag);
-    else
-        dedup_body<false>(gtable + tbase[qi], cap, terms, w0, nw, uterms, hashes, ts, seeds,
-                          &lcount, &lflag);
-    __syncthreads();
-    if (threadIdx.x == 0) nterms[qi] = lcount;
+    if (cap <= kLdsTableSlots) {
+        if (threadIdx.x == 0) { lcount = 0; lflag = kEmpty; }
+        for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) ltable[s] = kEmpty;
+        __syncthreads();
+        dedup_range(ltable, cap, &lflag, terms, w0, 0, nw, uterms, hashes, ts, seeds, &lcount);
+        __syncthreads();
+        if (threadIdx.x == 0) nterms[qi] = lcount;
+        return;
+    }
+    uint64_t *table = gtable + tbase[qi];
+    const uint64_t b = (uint64_t)part * kDedupWindowsPerGroup;
+    const uint64_t e = min(nw, b + kDedupWindowsPerGroup);
+    dedup_range(table, cap, table + cap, terms, w0, b, e, uterms, hashes, ts, seeds, &nterms[qi]);
 }
 
 // ---- plan ------------------------------------------------------------------------------
 
 __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, const uint64_t *wbase,
-                                                    uint32_t n, uint32_t chunk, uint32_t n_slices,
+                                                    const uint32_t *slot, uint32_t n,
+                                                    uint32_t chunk, uint32_t n_slices,
                                                     uint32_t k_num, uint32_t k_den,
                                                     uint64_t ell_limit, QInfo *qinfo,
                                                     uint32_t *chunk_prefix, uint64_t *total_items,
@@ -242,7 +272,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, cons
         qi.hbase = wbase[q];
         qi.ell = ell;
         qi.nch = nch;
-        qi.pbase = nch > 1 ? pbase : 0xFFFFFFFFu;
+        qi.pbase = nch > 1 ? (slot ? slot[q] : pbase) : 0xFFFFFFFFu;
         qi.thr = thr > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)thr;
         qinfo[q] = qi;
         chunk_prefix[q] = cbase;
@@ -436,19 +466,21 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 
         // Several chunks of one (query, slice): each adds its counts into the
         // query's score buffer (device-scope atomics; document (lane, d, bit)
-        // at (d*32 + bit)*64 + lane, so one instruction's 64 lanes touch 256
-        // consecutive bytes); the last chunk to finish reads the totals back
+        // at (d*32 + bit)*lanes + lane, so one instruction's lanes touch
+        // consecutive words); the last chunk to finish reads the totals back
         // into bit planes and clears the buffer for the next batch.  The cost
-        // of the merge does not grow with the number of chunks.
+        // of the merge does not grow with the number of chunks.  Lanes past
+        // the slice's documents hold zero counts and touch nothing.
         if (qn.nch > 1) {
-            uint32_t *acc = a.accum + ((uint64_t)qn.pbase * a.n_slices + sl) * kSliceDocs;
+            const uint32_t L = uniform_u32(sd.lanes);
+            uint32_t *acc = a.accum + (uint64_t)qn.pbase * a.acc_words + uniform_u32(sd.acc_off);
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
 #pragma unroll 4
                 for (int bit = 0; bit < 32; ++bit) {
                     const uint32_t c = cnt.score(d, bit);
                     if (c)
-                        __hip_atomic_fetch_add(acc + (d * 32 + bit) * 64 + lane, c, __ATOMIC_RELAXED,
+                        __hip_atomic_fetch_add(acc + (d * 32 + bit) * L + lane, c, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
@@ -460,15 +492,17 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
             __threadfence();
             if (lane == 0) a.tickets[(uint64_t)qi * a.n_slices + sl] = 0;   // ready for reuse
             cnt.clear();
+            if (lane < L) {
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
+                for (int d = 0; d < 4; ++d) {
 #pragma unroll 4
-                for (int bit = 0; bit < 32; ++bit) {
-                    uint32_t *cell = acc + (d * 32 + bit) * 64 + lane;
-                    const uint32_t c = __hip_atomic_load(cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    *cell = 0;
+                    for (int bit = 0; bit < 32; ++bit) {
+                        uint32_t *cell = acc + (d * 32 + bit) * L + lane;
+                        const uint32_t c = __hip_atomic_load(cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        *cell = 0;
 #pragma unroll
-                    for (int p = 0; p < P; ++p) cnt.H[p][d] |= ((c >> p) & 1u) << bit;
+                        for (int p = 0; p < P; ++p) cnt.H[p][d] |= ((c >> p) & 1u) << bit;
+                    }
                 }
             }
         }
@@ -702,8 +736,8 @@ __global__ __launch_bounds__(256) void count_kernel(const uint8_t *bytes, const 
             const uint64_t t = window_term(bytes + sd.byte_off + (w - sd.wbase), ts, ok);
             if (ok) {
                 const uint64_t cap = 1ull << tlog2[d];
-                uniq = set_insert<false>(table + tbase[d], cap, t, mix64(t) & (cap - 1),
-                                         &empty_flag[d]);
+                uniq = t == kEmpty ? atomicOr(&empty_flag[d], 1u) == 0
+                                   : set_insert(table + tbase[d], cap, t, mix64(t) & (cap - 1));
             }
         }
         const uint32_t d0 = uniform_u32(d);
@@ -800,32 +834,57 @@ int occ_of_p(int unroll, int h)
 
 hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const uint64_t *wbase,
                           uint32_t n_queries, uint64_t W, TermSpec ts, uint64_t *terms,
-                          hipStream_t st)
+                          uint32_t *nterms, hipStream_t st)
 {
-    if (W == 0) return hipSuccess;
-    hipLaunchKernelGGL(extract_kernel, dim3(grid_for(W, 256)), dim3(256), 0, st, bytes, qstart,
-                       wbase, n_queries, W, ts, terms);
+    if (n_queries == 0) return hipSuccess;
+    hipLaunchKernelGGL(extract_kernel, dim3(grid_for(std::max<uint64_t>(W, n_queries), 256)),
+                       dim3(256), 0, st, bytes, qstart, wbase, n_queries, W, ts, terms, nterms);
     return hipGetLastError();
 }
 
 hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint64_t *tbase,
-                        uint64_t *table, uint64_t *uterms, uint64_t *hashes, uint32_t *nterms,
-                        uint32_t n_queries, TermSpec ts, Seeds seeds, hipStream_t st)
+                        const uint32_t *bprefix, uint32_t n_groups, uint64_t *table,
+                        uint64_t table_slots, uint64_t *uterms, uint64_t *hashes,
+                        uint32_t *nterms, uint32_t n_queries, TermSpec ts, Seeds seeds,
+                        hipStream_t st)
 {
     if (n_queries == 0) return hipSuccess;
-    hipLaunchKernelGGL(dedup_kernel, dim3(n_queries), dim3(256), 0, st, terms, wbase, tbase,
-                       table, uterms, hashes, nterms, ts, seeds);
+    if (table_slots) {
+        hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(table_slots, 256)), dim3(256), 0, st,
+                           table, table_slots, kEmpty);
+    }
+    hipLaunchKernelGGL(dedup_kernel, dim3(n_groups), dim3(256), 0, st, terms, wbase, tbase,
+                       bprefix, n_queries, table, uterms, hashes, nterms, ts, seeds);
     return hipGetLastError();
 }
 
-hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, uint32_t n_queries,
-                       uint32_t chunk, uint32_t n_slices, uint32_t k_num, uint32_t k_den,
-                       uint64_t ell_limit, QInfo *qinfo, uint32_t *chunk_prefix,
+uint64_t score_buffer_words(const SliceDesc *slices, uint32_t n_slices)
+{
+    uint64_t w = 0;
+    for (uint32_t i = 0; i < n_slices; ++i) w += 128ull * slices[i].lanes;
+    return w;
+}
+
+uint64_t dedup_table_slots(uint64_t windows)
+{
+    const uint64_t cap = table_cap(windows);
+    return cap <= kLdsTableSlots ? 0 : cap + 1;
+}
+
+uint32_t dedup_groups(uint64_t windows)
+{
+    if (table_cap(windows) <= kLdsTableSlots) return 1;
+    return (uint32_t)std::max<uint64_t>(1, (windows + kDedupWindowsPerGroup - 1) / kDedupWindowsPerGroup);
+}
+
+hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, const uint32_t *slot,
+                       uint32_t n_queries, uint32_t chunk, uint32_t n_slices, uint32_t k_num,
+                       uint32_t k_den, uint64_t ell_limit, QInfo *qinfo, uint32_t *chunk_prefix,
                        uint64_t *total_items, unsigned long long *work_counter,
                        unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags,
                        hipStream_t st)
 {
-    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, nterms, wbase, n_queries, chunk,
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, nterms, wbase, slot, n_queries, chunk,
                        n_slices, k_num, k_den, ell_limit, qinfo, chunk_prefix, total_items,
                        work_counter, cand_counter, qcount, flags);
     return hipGetLastError();

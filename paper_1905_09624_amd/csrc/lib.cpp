@@ -405,8 +405,15 @@ cobs_status cobs_builder_plan(cobs_builder *b)
             sd.ndocs = (uint32_t)(dfirst < blk.docs ? std::min<uint64_t>(kSliceBytes * 8, blk.docs - dfirst) : 0);
             sd.doc0 = blk.first + (uint32_t)dfirst;
             sd.block = k;
+            sd.lanes = (sd.ndocs + 127) / 128;
+            sd.acc_off = (uint32_t)ix->acc_words;
+            ix->acc_words += 128ull * sd.lanes;
             ix->slices.push_back(sd);
         }
+    }
+    if (ix->acc_words > 0xFFFFFFFFull) {
+        delete ix;
+        return set_error(COBS_EINVAL, "too many documents for one index");
     }
     ix->total_bytes = off;
     b->ix = ix;
@@ -502,6 +509,7 @@ cobs_status cobs_index_info(const cobs_index *ix, cobs_index_info_t *info)
     info->n_blocks = (uint32_t)ix->blocks.size();
     info->params = ix->prm;
     info->total_bytes = ix->total_bytes;
+    info->score_bytes = ix->acc_words * 4;
     return COBS_OK;
 }
 
@@ -569,6 +577,12 @@ struct Scalars {
     uint32_t pad;
 };
 
+size_t batch_meta_bytes(uint32_t n)
+{
+    return ((size_t)n * 8 + (size_t)(n + 1) * 8 + (size_t)n * 8 + (size_t)(n + 1) * 4 +
+            (size_t)n * 4 + 15) & ~size_t(15);
+}
+
 uint32_t auto_chunk(uint64_t W, uint32_t n, uint32_t n_slices, int grid)
 {
     // enough work items to fill the persistent grid twice, chunks of <= 1024
@@ -622,10 +636,17 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     }
     wbase[n] = W;
     std::vector<uint64_t> tb(n, 0);
+    std::vector<uint32_t> bprefix(n + 1, 0);
+    uint64_t groups = 0;
     for (uint32_t i = 0; i < n; ++i) {
-        const uint64_t cap = dedup_table_cap(wbase[i + 1] - wbase[i]);
-        if (cap > kLdsTableSlots) { tb[i] = tslots; tslots += cap; }
+        const uint64_t nw = wbase[i + 1] - wbase[i];
+        tb[i] = tslots;
+        tslots += dedup_table_slots(nw);
+        bprefix[i] = (uint32_t)groups;
+        groups += dedup_groups(nw);
     }
+    if (groups > 0x7FFFFFFFull) return set_error(COBS_EINVAL, "query batch too large");
+    bprefix[n] = (uint32_t)groups;
     const int planes = gather_planes_for(maxw);
     int unroll = b.unroll ? (int)b.unroll : (ix->tuned_unroll ? ix->tuned_unroll : gather_default_unroll((int)h));
     if (!gather_unroll_valid(unroll, (int)h)) unroll = gather_default_unroll((int)h);
@@ -643,18 +664,24 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     const TermSpec ts = term_spec(ix->prm);
 
     // uploads
-    const size_t meta = (size_t)(2 * n + 1) * 8 + (size_t)n * 8;
+    // staging: qstart | wbase | tbase | bprefix | slot | query bytes (host mode)
+    const size_t o_wb = (size_t)n * 8, o_tb = o_wb + (size_t)(n + 1) * 8, o_bp = o_tb + (size_t)n * 8;
+    const size_t o_sl = o_bp + (size_t)(n + 1) * 4;
+    const size_t meta = batch_meta_bytes(n);
     COBS_HIP(ws.h_stage.ensure(meta + (b.mem == COBS_MEM_HOST ? nbytes : 0)));
     uint8_t *stg = ws.h_stage.as<uint8_t>();
     std::memcpy(stg, qstart, (size_t)n * 8);
-    std::memcpy(stg + (size_t)n * 8, wbase, (size_t)(n + 1) * 8);
-    std::memcpy(stg + (size_t)(2 * n + 1) * 8, tb.data(), (size_t)n * 8);
-    COBS_HIP(ws.qstart.ensure((size_t)n * 8));
-    COBS_HIP(ws.wbase.ensure((size_t)(n + 1) * 8));
-    COBS_HIP(ws.tbase.ensure((size_t)n * 8));
-    COBS_HIP(hipMemcpyAsync(ws.qstart.p, stg, (size_t)n * 8, hipMemcpyHostToDevice, st));
-    COBS_HIP(hipMemcpyAsync(ws.wbase.p, stg + (size_t)n * 8, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, st));
-    COBS_HIP(hipMemcpyAsync(ws.tbase.p, stg + (size_t)(2 * n + 1) * 8, (size_t)n * 8, hipMemcpyHostToDevice, st));
+    std::memcpy(stg + o_wb, wbase, (size_t)(n + 1) * 8);
+    std::memcpy(stg + o_tb, tb.data(), (size_t)n * 8);
+    std::memcpy(stg + o_bp, bprefix.data(), (size_t)(n + 1) * 4);
+    if (b.slots) std::memcpy(stg + o_sl, b.slots, (size_t)n * 4);
+    COBS_HIP(ws.meta.ensure(meta));
+    COBS_HIP(hipMemcpyAsync(ws.meta.p, stg, meta, hipMemcpyHostToDevice, st));
+    const uint64_t *d_qstart = ws.meta.as<uint64_t>();
+    const uint64_t *d_wbase = (const uint64_t *)(ws.meta.as<uint8_t>() + o_wb);
+    const uint64_t *d_tbase = (const uint64_t *)(ws.meta.as<uint8_t>() + o_tb);
+    const uint32_t *d_bprefix = (const uint32_t *)(ws.meta.as<uint8_t>() + o_bp);
+    const uint32_t *d_slot = b.slots ? (const uint32_t *)(ws.meta.as<uint8_t>() + o_sl) : nullptr;
     const uint8_t *dbytes = b.bytes;
     if (b.mem == COBS_MEM_HOST) {
         COBS_HIP(ws.bytes.ensure(nbytes + 64));
@@ -671,10 +698,10 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     COBS_HIP(ws.hashes.ensure(std::max<uint64_t>(W, 1) * 8 * h));
     COBS_HIP(ws.nterms.ensure((size_t)n * 4));
     COBS_HIP(ws.table.ensure(std::max<uint64_t>(tslots, 1) * 8));
-    COBS_HIP(launch_extract(dbytes, ws.qstart.as<uint64_t>(), ws.wbase.as<uint64_t>(), n, W, ts,
-                            ws.terms.as<uint64_t>(), st));
-    COBS_HIP(launch_dedup(ws.terms.as<uint64_t>(), ws.wbase.as<uint64_t>(), ws.tbase.as<uint64_t>(),
-                          ws.table.as<uint64_t>(), ws.uterms.as<uint64_t>(),
+    COBS_HIP(launch_extract(dbytes, d_qstart, d_wbase, n, W, ts, ws.terms.as<uint64_t>(),
+                            ws.nterms.as<uint32_t>(), st));
+    COBS_HIP(launch_dedup(ws.terms.as<uint64_t>(), d_wbase, d_tbase, d_bprefix, (uint32_t)groups,
+                          ws.table.as<uint64_t>(), tslots, ws.uterms.as<uint64_t>(),
                           ws.hashes.as<uint64_t>(), ws.nterms.as<uint32_t>(), n, ts, ix->seeds, st));
     if (b.terms_out) {
         std::vector<uint32_t> nt(n);
@@ -696,10 +723,14 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     COBS_HIP(ws.scalars.ensure(sizeof(Scalars)));
     // score buffers of split queries: zero on allocation, left zero by every
     // complete gather launch
-    const uint64_t accum_words = pslots * n_slices * (uint64_t)kSliceDocs;
-    if (ws.accum_words < accum_words || !ws.accum.p) {
-        COBS_HIP(ws.accum.ensure(std::max<uint64_t>(accum_words, 64) * 4, true, st));
-        ws.accum_words = ws.accum.cap / 4;
+    uint32_t *accum = b.accum;
+    if (!accum) {
+        const uint64_t accum_words = pslots * ix->acc_words;
+        if (ws.accum_words < accum_words || !ws.accum.p) {
+            COBS_HIP(ws.accum.ensure(std::max<uint64_t>(accum_words, 64) * 4, true, st));
+            ws.accum_words = ws.accum.cap / 4;
+        }
+        accum = ws.accum.as<uint32_t>();
     }
     COBS_HIP(ws.qcount.ensure((size_t)n * 4));
     COBS_HIP(hipMemsetAsync(ws.scalars.p, 0, sizeof(Scalars), st));
@@ -711,7 +742,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     for (int attempt = 0;; ++attempt) {
         COBS_HIP(ws.cand_key.ensure(ws.cand_cap * 8));
         COBS_HIP(ws.cand_q.ensure(ws.cand_cap * 4));
-        COBS_HIP(launch_plan(ws.nterms.as<uint32_t>(), ws.wbase.as<uint64_t>(), n, C, n_slices,
+        COBS_HIP(launch_plan(ws.nterms.as<uint32_t>(), d_wbase, d_slot, n, C, n_slices,
                              b.k_num, b.k_den, ell_limit, ws.qinfo.as<QInfo>(),
                              ws.chunk_prefix.as<uint32_t>(), &dsc->total_items, &dsc->work_counter,
                              &dsc->cand_counter, ws.qcount.as<uint32_t>(), &dsc->flags, st));
@@ -729,7 +760,8 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         ga.total_items = &dsc->total_items;
         ga.work_counter = &dsc->work_counter;
         ga.tickets = ws.tickets.as<uint32_t>();
-        ga.accum = ws.accum.as<uint32_t>();
+        ga.accum = accum;
+        ga.acc_words = ix->acc_words;
         ga.cand_counter = &dsc->cand_counter;
         ga.cand_key = ws.cand_key.as<uint64_t>();
         ga.cand_q = ws.cand_q.as<uint32_t>();
@@ -831,6 +863,50 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         out.scores = ho + total;
         return COBS_OK;
     }
+}
+
+cobs_status reserve_workspace(cobs_index *ix, Workspace &ws, uint64_t W, uint32_t n,
+                              hipStream_t st)
+{
+    // upper bounds of what run_batch asks for: query bytes <= W + n * q,
+    // global dedup slots < 4 W + n (capacity < 4 windows, plus a flag word)
+    const uint32_t h = ix->prm.num_hashes;
+    const uint64_t nbytes = W + (uint64_t)n * ix->prm.q;
+    const uint64_t n_slices = ix->slices.size();
+    const size_t meta = batch_meta_bytes(n);
+    COBS_HIP(ws.h_stage.ensure(meta + nbytes));
+    COBS_HIP(ws.meta.ensure(meta));
+    COBS_HIP(ws.bytes.ensure(nbytes + 64));
+    COBS_HIP(ws.terms.ensure(std::max<uint64_t>(W, 1) * 8));
+    COBS_HIP(ws.uterms.ensure(std::max<uint64_t>(W, 1) * 8));
+    COBS_HIP(ws.hashes.ensure(std::max<uint64_t>(W, 1) * 8 * h));
+    COBS_HIP(ws.nterms.ensure((size_t)n * 4));
+    COBS_HIP(ws.table.ensure(std::max<uint64_t>(4 * W + n, 1) * 8));
+    if (ws.tickets_slots < (uint64_t)n * n_slices || !ws.tickets.p) {
+        COBS_HIP(ws.tickets.ensure(std::max<uint64_t>((uint64_t)n * n_slices, 1) * 4, true, st));
+        ws.tickets_slots = ws.tickets.cap / 4;
+    }
+    COBS_HIP(ws.qinfo.ensure((size_t)n * sizeof(QInfo)));
+    COBS_HIP(ws.chunk_prefix.ensure((size_t)(n + 1) * 4));
+    COBS_HIP(ws.scalars.ensure(sizeof(Scalars)));
+    COBS_HIP(ws.qcount.ensure((size_t)n * 4));
+    ws.cand_cap = std::max<uint64_t>(ws.cand_cap, std::max<uint64_t>(1 << 20, (uint64_t)n * 64));
+    COBS_HIP(ws.cand_key.ensure(ws.cand_cap * 8));
+    COBS_HIP(ws.cand_q.ensure(ws.cand_cap * 4));
+    COBS_HIP(ws.gstart.ensure((size_t)(n + 1) * 4));
+    COBS_HIP(ws.gcursor.ensure((size_t)n * 4));
+    COBS_HIP(ws.seg_a.ensure(ws.cand_cap * 8));
+    COBS_HIP(ws.seg_b.ensure(ws.cand_cap * 8));
+    COBS_HIP(ws.out_start.ensure((size_t)(n + 1) * 4));
+    COBS_HIP(ws.out_n.ensure((size_t)n * 4));
+    COBS_HIP(ws.out_id.ensure(ws.cand_cap * 4));
+    COBS_HIP(ws.out_score.ensure(ws.cand_cap * 4));
+    COBS_HIP(ws.h_small.ensure(sizeof(Scalars) + (size_t)n * 8 + (size_t)(n + 1) * 4));
+    COBS_HIP(ws.h_out.ensure(ws.cand_cap * 8));
+    for (hipEvent_t &e : ws.ev)
+        if (!e) COBS_HIP(hipEventCreate(&e));
+    COBS_HIP(hipStreamSynchronize(st));
+    return COBS_OK;
 }
 
 cobs_status make_hits(const BatchOut &o, uint32_t q0, uint32_t n, cobs_hits *dst)
@@ -1033,7 +1109,7 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
     if (!ix || !best) return set_error(COBS_EINVAL, "NULL argument");
     const int h = (int)ix->prm.num_hashes;
     const int unrolls[2] = {h == 1 ? 4 : 2, h == 1 ? 8 : 4};
-    const uint32_t chunks[6] = {0, 256, 512, 1024, 2048, 4096};
+    const uint32_t chunks[] = {0, 512, 1024, 2048, 4096, 8192, 16384, 1u << 20};
     Workspace *ws = acquire_workspace(ix);
     cobs_tuning win{0, 0, 1e300};
     cobs_status s = COBS_OK;

@@ -56,7 +56,7 @@ struct Block {
 
 // Everything one query batch needs on the device; reused across batches.
 struct Workspace {
-    DevBuf bytes, qstart, wbase, terms, uterms, hashes, nterms, table, tbase;
+    DevBuf bytes, meta, terms, uterms, hashes, nterms, table;
     DevBuf tickets, qinfo, chunk_prefix, scalars, accum;
     DevBuf cand_key, cand_q, qcount, gstart, gcursor, seg_a, seg_b;
     DevBuf out_start, out_n, out_id, out_score, full;
@@ -88,6 +88,8 @@ struct BatchSpec {
     uint32_t unroll = 0;               // terms in flight per wavefront; 0 = tuned or default
     uint32_t *full_scores = nullptr;   // host [n * n_docs]: full score mode
     uint64_t *terms_out = nullptr;     // host [windows]: terms-only mode
+    const uint32_t *slots = nullptr;   // host [n]: score-buffer slot of each query in accum
+    uint32_t *accum = nullptr;         // device score buffers (zero); NULL = the workspace's
     bool time_gather = false;          // HIP events around the gather launch
 };
 
@@ -108,6 +110,7 @@ struct cobs_index {
     cobs::Seeds seeds{};
     int tuned_unroll = 0;              // set by cobs_tune (0 = default)
     uint32_t tuned_chunk = 0;          // set by cobs_tune (0 = automatic)
+    uint64_t acc_words = 0;            // words of one query's score buffer
     std::mutex pool_mu;
     std::vector<cobs::Workspace *> pool;
     ~cobs_index();
@@ -121,6 +124,11 @@ void release_workspace(cobs_index *ix, Workspace *ws);
 // Run one query batch end to end on stream st (synchronises st).
 cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStream_t st,
                       BatchOut &out);
+
+// Grow every buffer of ws for batches of up to max_queries queries holding
+// max_windows windows in total, so that such batches allocate nothing.
+cobs_status reserve_workspace(cobs_index *ix, Workspace &ws, uint64_t max_windows,
+                              uint32_t max_queries, hipStream_t st);
 
 // Fill library-owned cobs_hits from a BatchOut (queries [q0, q0+n)).
 cobs_status make_hits(const BatchOut &o, uint32_t q0, uint32_t n, cobs_hits *dst);

@@ -1,13 +1,16 @@
 // Continuous-batching server over a resident COBS index.
 //
-// Requests are copied at submit time and admitted in arrival order while the
-// score memory they reserve (n_docs * 4 bytes each, the size of one query's
-// full score vector) fits the budget.  Each of num_streams workers owns a HIP
-// stream and a workspace; a free worker takes every admitted request that
-// shares the head request's options (K, top-k), up to the batch limits, and
-// runs them as one device batch.  While one worker's batch is on the GPU the
-// next worker collects the requests that arrived meanwhile, so new arrivals
-// join the next batch instead of waiting for a queue to drain.
+// The score budget is one device pool of per-query score buffers (one
+// query's counts over every document, the memory a query split over several
+// work items accumulates into).  Requests are copied at submit time and
+// admitted in arrival order while a buffer is free; each holds its buffer
+// until its result is ready.  Each of num_streams workers owns a HIP stream
+// and a workspace sized at start for the batch limits; a free worker takes
+// every admitted request that shares the head request's options (K, top-k),
+// up to the batch limits, and runs them as one device batch.  While one
+// worker's batch is on the GPU the next worker collects the requests that
+// arrived meanwhile, so new arrivals join the next batch instead of waiting
+// for a queue to drain.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -30,7 +33,7 @@ struct Request {
     std::vector<uint8_t> bytes;
     uint32_t k_num = 0, k_den = 1, topk = 0;
     uint64_t arrival_ns = 0, done_ns = 0;
-    uint64_t reserve = 0;
+    uint32_t slot = 0;                 // score buffer held while admitted
     bool done = false;
     cobs_status status = COBS_OK;
     std::string error;
@@ -42,7 +45,9 @@ struct Request {
 struct cobs_server {
     cobs_index *ix = nullptr;
     cobs_serve_opts opts{};
-    uint64_t budget = 0, used = 0;
+    DevBuf pool;                       // n_slots score buffers, zero between batches
+    uint64_t n_slots = 0;
+    std::vector<uint32_t> free_slots;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Request>> waiting;    // not yet admitted
@@ -59,8 +64,9 @@ struct cobs_server {
 
     void admit_locked()
     {
-        while (!waiting.empty() && used + waiting.front()->reserve <= budget) {
-            used += waiting.front()->reserve;
+        while (!waiting.empty() && !free_slots.empty()) {
+            waiting.front()->slot = free_slots.back();
+            free_slots.pop_back();
             ready.push_back(waiting.front());
             waiting.pop_front();
         }
@@ -78,6 +84,7 @@ void cobs_server::worker(int lane)
     std::vector<std::shared_ptr<Request>> batch;
     std::vector<uint8_t> bytes;
     std::vector<uint64_t> off;
+    std::vector<uint32_t> slots;
     for (;;) {
         batch.clear();
         {
@@ -105,9 +112,11 @@ void cobs_server::worker(int lane)
         }
         bytes.clear();
         off.assign(1, 0);
+        slots.clear();
         for (auto &r : batch) {
             bytes.insert(bytes.end(), r->bytes.begin(), r->bytes.end());
             off.push_back(bytes.size());
+            slots.push_back(r->slot);
         }
         BatchSpec spec;
         spec.bytes = bytes.data();
@@ -118,6 +127,8 @@ void cobs_server::worker(int lane)
         spec.k_den = batch[0]->k_den;
         spec.topk = batch[0]->topk;
         spec.score_bits = opts.score_bits;
+        spec.slots = slots.data();
+        spec.accum = pool.as<uint32_t>();
         BatchOut bo;
         cobs_status s = run_batch(ix, *ws, spec, st, bo);
         std::string err = s == COBS_OK ? "" : cobs_last_error();
@@ -135,7 +146,7 @@ void cobs_server::worker(int lane)
                 r.error = err;
                 r.done = true;
                 r.done_ns = t;
-                used -= r.reserve;
+                free_slots.push_back(r.slot);
                 if (per[i] == COBS_OK) {
                     ++completed;
                     lookups += r.hits.num_terms;
@@ -165,30 +176,48 @@ cobs_status cobs_serve(cobs_index *ix, const cobs_serve_opts *opts, cobs_server 
         return set_error(COBS_EINVAL, "num_streams must be <= 8");
     }
     if (s->opts.max_batch_queries == 0) s->opts.max_batch_queries = 4096;
-    if (s->opts.max_batch_terms == 0) s->opts.max_batch_terms = 1ull << 25;
+    if (s->opts.max_batch_terms == 0) s->opts.max_batch_terms = 1ull << 23;
     if (s->opts.score_bits == 0) s->opts.score_bits = 32;
     if (s->opts.score_bits != 16 && s->opts.score_bits != 32) {
         delete s;
         return set_error(COBS_EINVAL, "score_bits must be 16 or 32");
     }
     (void)hipSetDevice(ix->device);
-    s->budget = s->opts.score_budget_bytes;
-    if (s->budget == 0) {
+    const uint64_t slot_bytes = std::max<uint64_t>(ix->acc_words * 4, 4);
+    uint64_t budget = s->opts.score_budget_bytes;
+    if (budget == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 1ull << 32;
-        s->budget = fr / 4;
+        budget = std::min<uint64_t>(4096 * slot_bytes, fr / 4);
     }
+    s->n_slots = std::min<uint64_t>(budget / slot_bytes, 1u << 30);
+    auto fail = [&](cobs_status st) {
+        for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+        for (Workspace *w : s->spaces) delete w;
+        delete s;
+        return st;
+    };
     for (uint32_t i = 0; i < s->opts.num_streams; ++i) {
         hipStream_t st;
         hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-        if (e != hipSuccess) {
-            for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
-            delete s;
-            return hip_error(e, "hipStreamCreateWithFlags");
-        }
+        if (e != hipSuccess) return fail(hip_error(e, "hipStreamCreateWithFlags"));
         s->streams.push_back(st);
         s->spaces.push_back(new Workspace());
     }
+    if (s->n_slots) {
+        hipError_t e = s->pool.ensure(s->n_slots * slot_bytes, true, s->streams[0]);
+        if (e != hipSuccess) return fail(hip_error(e, "score buffer pool"));
+        s->free_slots.reserve(s->n_slots);
+        for (uint64_t i = s->n_slots; i-- > 0;) s->free_slots.push_back((uint32_t)i);
+    }
+    for (uint32_t i = 0; i < s->opts.num_streams; ++i) {
+        const uint64_t w = s->opts.max_batch_terms;
+        const uint32_t nq = (uint32_t)std::min<uint64_t>(s->opts.max_batch_queries, s->n_slots + 1);
+        cobs_status st = reserve_workspace(ix, *s->spaces[i], w, nq, s->streams[i]);
+        if (st != COBS_OK) return fail(st);
+    }
+    if (hipStreamSynchronize(s->streams[0]) != hipSuccess)
+        return fail(set_error(COBS_EDEVICE, "stream synchronisation failed"));
     for (uint32_t i = 0; i < s->opts.num_streams; ++i)
         s->workers.emplace_back(&cobs_server::worker, s, (int)i);
     *out = s;
@@ -206,14 +235,13 @@ cobs_status cobs_submit(cobs_server *s, const uint8_t *query, uint64_t len, uint
     r->k_den = k_den;
     r->topk = topk;
     r->arrival_ns = arrival_ns ? arrival_ns : now_ns();
-    r->reserve = (uint64_t)s->ix->n_docs * 4;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) return set_error(COBS_ECANCELLED, "server is stopping");
         ++s->submitted;
-        if (r->reserve > s->budget) {
+        if (s->n_slots == 0) {
             ++s->rejected;
-            return set_error(COBS_EBUDGET, "request exceeds the score memory budget");
+            return set_error(COBS_EBUDGET, "the score memory budget holds no score buffer");
         }
         r->ticket = s->next_ticket++;
         s->first_arrival = std::min(s->first_arrival, r->arrival_ns);

@@ -147,7 +147,12 @@ def test_bytes_terms_with_all_ones_term():
     d = oracle.Docs.from_lists([b"\xff" * 40 + b"abcdefghij"])
     prm = cobs.make_params(1, 8, False, 3, 0.1, 0, 3)
     gix = cobs.Index.build(prm, d.bytes, d.str_off, d.doc_str)
-    qs = [b"\xff" * 20, b"\xff" * 9 + b"abc", b"xyz"]
+    rng = np.random.default_rng(12)
+    # the last query: a global dedup table spread over several workgroups,
+    # with the all-ones term in more than one of them
+    long_q = (b"\xff" * 9000 + rng.integers(0, 256, 12000, dtype=np.uint8).tobytes()
+              + b"\xff" * 9000)
+    qs = [b"\xff" * 20, b"\xff" * 9 + b"abc", b"xyz", long_q]
     data, off = queries_of(qs)
     got = gix.terms(data, off, q=8)
     for i, s in enumerate(qs):

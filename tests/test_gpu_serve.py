@@ -75,7 +75,16 @@ def test_same_result_alone_and_in_a_mix(served):
 
 def test_admission_by_score_memory(served):
     cobs, ix, qs, oix = served
-    per_query = ix.info()["n_docs"] * 4
+    info = ix.info()
+    per_query = info["score_bytes"]
+    # 4 bytes per document, each block's 8192-document slices rounded up to
+    # whole 128-document lanes
+    want = 0
+    for b in range(info["n_blocks"]):
+        docs = ix.block(b)["docs"]
+        for s0 in range(0, docs, 8192):
+            want += 4 * 128 * (-(-min(8192, docs - s0) // 128))
+    assert per_query == want >= 4 * info["n_docs"]
     with pytest.raises(cobs.CobsError) as e:
         srv = cobs.Server(ix, budget_bytes=per_query - 1)
         try:
