@@ -171,6 +171,9 @@ cobs_status cobs_index_read(const cobs_index *ix, uint64_t offset, uint64_t nbyt
  *               (persistent gather kernel); COBS_MODE_PLAIN runs the same
  *               pipeline once per query (one query per launch).
  *  mem          where `bytes` lives (cobs_mem); q_off is always host memory.
+ *  chunk        distinct terms per work item of the gather kernel for this
+ *               call; 0 = the index's split (see cobs_tuning).  Results
+ *               never depend on it.
  */
 typedef struct {
     uint32_t k_num;
@@ -179,6 +182,7 @@ typedef struct {
     uint32_t score_bits;
     uint32_t mode;
     uint32_t mem;
+    uint32_t chunk;
 } cobs_query_opts;
 
 /* Hits of one query, ordered by (score desc, input id asc). */
@@ -310,9 +314,11 @@ cobs_status cobs_serve_replay(cobs_server *s, const uint8_t *bytes, const uint64
 
 /*
  * Launch shape of the gather kernel for an index: `unroll` terms whose rows
- * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4) and `chunk`
- * distinct terms per work item (longer queries are split and their partial
- * counters merged).  0 = automatic.  Results never depend on either.
+ * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4) and `chunk`,
+ * the most distinct terms per work item (longer queries are split and their
+ * counts merged; a batch is split into about four work items per resident
+ * wavefront, with items of at most `chunk` terms).  0 = defaults (8 or 2;
+ * 16384).  Results never depend on either.
  */
 typedef struct {
     uint32_t unroll;
@@ -321,10 +327,8 @@ typedef struct {
 } cobs_tuning;
 
 /* Time the gather kernel on the sample batch for every supported unroll and
- * chunk in {automatic, 512, 1024, 2048, 4096, 8192, 16384, 2^20}, keep the
- * fastest pair for this index, report it in *best.  A tuned chunk applies to
- * batches with at least two work items per resident wavefront; smaller
- * batches keep the automatic split, which spreads long queries over the GPU.
+ * chunk in {default, 512, 1024, 2048, 4096, 8192, 16384, 2^20}, keep the
+ * fastest pair for this index, report it in *best.
  * The sample should resemble the batches to come (a separate query set). */
 cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
                       uint32_t n_queries, uint32_t mem, void *stream, cobs_tuning *best);

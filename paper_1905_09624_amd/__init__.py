@@ -48,7 +48,8 @@ class IndexInfo(C.Structure):
 
 class QueryOpts(C.Structure):
     _fields_ = [("k_num", C.c_uint32), ("k_den", C.c_uint32), ("topk", C.c_uint32),
-                ("score_bits", C.c_uint32), ("mode", C.c_uint32), ("mem", C.c_uint32)]
+                ("score_bits", C.c_uint32), ("mode", C.c_uint32), ("mem", C.c_uint32),
+                ("chunk", C.c_uint32)]
 
 
 class Hits(C.Structure):
@@ -273,14 +274,14 @@ class Index:
         _check(lib().cobs_set_tuning(self._h, C.byref(t)))
 
     def query_flat(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
-                   stream=None):
+                   stream=None, chunk=0):
         """Hits of every query in flat arrays: (num_terms[n], hit_off[n+1],
         doc_ids[total], scores[total]); query i's hits are
         doc_ids[hit_off[i]:hit_off[i+1]]."""
         ptr, mem, keep = _byte_source(data)
         qo = np.ascontiguousarray(q_off, dtype=np.uint64)
         n = len(qo) - 1
-        opts = QueryOpts(k[0], k[1], topk, score_bits, mode, mem)
+        opts = QueryOpts(k[0], k[1], topk, score_bits, mode, mem, chunk)
         r = C.c_void_p()
         _check(lib().cobs_query_results(self._h, ptr, _p(qo), n, C.byref(opts), _stream(stream),
                                         C.byref(r)))
@@ -304,19 +305,19 @@ class Index:
             lib().cobs_results_free(r)
 
     def query(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
-              stream=None):
+              stream=None, chunk=0):
         """Hits of every query: list of (doc_ids, scores, num_terms)."""
-        nt, off, ids, sc = self.query_flat(data, q_off, k, topk, score_bits, mode, stream)
+        nt, off, ids, sc = self.query_flat(data, q_off, k, topk, score_bits, mode, stream, chunk)
         return [(ids[off[i]:off[i + 1]], sc[off[i]:off[i + 1]], int(nt[i]))
                 for i in range(len(nt))]
 
     def query_hits(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
-                   stream=None):
+                   stream=None, chunk=0):
         """The same through cobs_query_batch (one cobs_hits per query)."""
         ptr, mem, keep = _byte_source(data)
         qo = np.ascontiguousarray(q_off, dtype=np.uint64)
         n = len(qo) - 1
-        opts = QueryOpts(k[0], k[1], topk, score_bits, mode, mem)
+        opts = QueryOpts(k[0], k[1], topk, score_bits, mode, mem, chunk)
         out = C.POINTER(Hits)()
         _check(lib().cobs_query_batch(self._h, ptr, _p(qo), n, C.byref(opts), _stream(stream),
                                       C.byref(out)))

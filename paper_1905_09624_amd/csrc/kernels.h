@@ -14,6 +14,7 @@ constexpr uint32_t kLdsTableSlots = 8192;  // dedup table held in LDS (64 KiB)
 constexpr uint32_t kSortRun = 2048;        // candidates sorted in LDS per run
 constexpr uint32_t kSliceDocs = 8192;      // documents per slice (score buffer stride)
 constexpr uint32_t kDedupWindowsPerGroup = 8192;  // windows per workgroup of a global-table query
+constexpr uint32_t kDefaultChunkCap = 16384;      // largest automatic work item (terms)
 
 struct Seeds {
     uint64_t s[kMaxHashes];
@@ -76,7 +77,8 @@ struct GatherArgs {
     const uint32_t *order;
     const uint64_t *hashes;
     const QInfo *qinfo;
-    const uint32_t *chunk_prefix;      // [n_queries + 1]
+    const uint32_t *qorder;            // [n_queries] work order of the queries
+    const uint32_t *chunk_prefix;      // [n_queries + 1], in qorder order
     const uint64_t *total_items;       // device scalar
     unsigned long long *work_counter;  // device scalar
     uint32_t *tickets;                 // [n_queries * n_slices]
@@ -118,14 +120,15 @@ uint32_t dedup_groups(uint64_t windows);       // workgroups of the query
 // complete gather launch leaves them zero again.
 
 // Per-query chunks, thresholds, score-buffer slots, work totals; zeroes
-// counters.  A query split into several chunks uses score buffer slot[i] when
+// counters.  qorder: the queries by size class, largest first (work items
+// follow that order); chunk_prefix[i]: first chunk of query qorder[i].  A query split into several chunks uses score buffer slot[i] when
 // slot is non-NULL, else the next free one in query order.
 hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, const uint32_t *slot,
                        uint32_t n_queries, uint32_t chunk, uint32_t n_slices, uint32_t k_num,
-                       uint32_t k_den, uint64_t ell_limit, QInfo *qinfo, uint32_t *chunk_prefix,
-                       uint64_t *total_items, unsigned long long *work_counter,
-                       unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags,
-                       hipStream_t st);
+                       uint32_t k_den, uint64_t ell_limit, QInfo *qinfo, uint32_t *qorder,
+                       uint32_t *chunk_prefix, uint64_t *total_items,
+                       unsigned long long *work_counter, unsigned long long *cand_counter,
+                       uint32_t *qcount, uint32_t *flags, hipStream_t st);
 
 // a5-a8: persistent gather / AND / ADD / threshold-or-top-k kernel.
 // planes: counter planes (>= bits of the largest l); unroll: terms whose rows

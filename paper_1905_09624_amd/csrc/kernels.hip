@@ -230,43 +230,57 @@ __global__ __launch_bounds__(256) void dedup_kernel(const uint64_t *terms, const
 
 // ---- plan ------------------------------------------------------------------------------
 
+// Work items are ordered by query size class (floor(log2 l), largest first;
+// the order within a class is arbitrary), so the last items to start are
+// the smallest and the persistent grid drains evenly.
+__device__ __forceinline__ uint32_t size_class(uint32_t ell) { return __clz(ell); }   // 0..32
+
 __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, const uint64_t *wbase,
                                                     const uint32_t *slot, uint32_t n,
                                                     uint32_t chunk, uint32_t n_slices,
                                                     uint32_t k_num, uint32_t k_den,
                                                     uint64_t ell_limit, QInfo *qinfo,
-                                                    uint32_t *chunk_prefix, uint64_t *total_items,
+                                                    uint32_t *qorder, uint32_t *chunk_prefix,
+                                                    uint64_t *total_items,
                                                     unsigned long long *work_counter,
                                                     unsigned long long *cand_counter,
                                                     uint32_t *qcount, uint32_t *flags)
 {
-    __shared__ uint32_t s_ch[1024], s_ps[1024];
+    __shared__ uint32_t s_scan[1024];
+    __shared__ uint32_t s_class[33];
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
     const uint32_t per = (n + nt - 1) / nt;
     const uint32_t a = min(n, tid * per), b = min(n, a + per);
-    uint32_t sc = 0, sp = 0;
+    auto chunks_of = [&](uint32_t ell) { return ell ? (ell + chunk - 1) / chunk : 0u; };
+    // inclusive Hillis-Steele scan of one value per thread; returns the exclusive prefix
+    auto scan = [&](uint32_t v) -> uint32_t {
+        s_scan[tid] = v;
+        __syncthreads();
+        for (uint32_t o = 1; o < nt; o <<= 1) {
+            const uint32_t x = tid >= o ? s_scan[tid - o] : 0u;
+            __syncthreads();
+            s_scan[tid] += x;
+            __syncthreads();
+        }
+        const uint32_t r = s_scan[tid] - v;
+        __syncthreads();
+        return r;
+    };
+
+    // per-query state in input order; score-buffer slots of split queries
+    if (tid < 33) s_class[tid] = 0;
+    __syncthreads();
+    uint32_t sp = 0;
     for (uint32_t q = a; q < b; ++q) {
         const uint32_t ell = nterms[q];
-        const uint32_t nch = ell ? (ell + chunk - 1) / chunk : 0;
-        sc += nch;
-        sp += nch > 1 ? 1u : 0u;
+        sp += chunks_of(ell) > 1 ? 1u : 0u;
+        atomicAdd(&s_class[size_class(ell)], 1u);
     }
-    s_ch[tid] = sc;
-    s_ps[tid] = sp;
-    __syncthreads();
-    for (uint32_t o = 1; o < nt; o <<= 1) {   // inclusive Hillis-Steele scan
-        uint32_t x = 0, y = 0;
-        if (tid >= o) { x = s_ch[tid - o]; y = s_ps[tid - o]; }
-        __syncthreads();
-        s_ch[tid] += x;
-        s_ps[tid] += y;
-        __syncthreads();
-    }
-    uint32_t cbase = s_ch[tid] - sc, pbase = s_ps[tid] - sp;
+    uint32_t pbase = scan(sp);
     uint32_t bad = 0;
     for (uint32_t q = a; q < b; ++q) {
         const uint32_t ell = nterms[q];
-        const uint32_t nch = ell ? (ell + chunk - 1) / chunk : 0;
+        const uint32_t nch = chunks_of(ell);
         const uint64_t thr = ((uint64_t)k_num * ell + k_den - 1) / k_den;
         QInfo qi;
         qi.hbase = wbase[q];
@@ -275,16 +289,36 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, cons
         qi.pbase = nch > 1 ? (slot ? slot[q] : pbase) : 0xFFFFFFFFu;
         qi.thr = thr > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)thr;
         qinfo[q] = qi;
-        chunk_prefix[q] = cbase;
         qcount[q] = 0;
-        cbase += nch;
         pbase += nch > 1 ? 1u : 0u;
         bad |= (uint64_t)ell > ell_limit;
     }
     if (bad) atomicOr(flags, 1u);
+
+    // counting sort of the queries by size class
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < 33; ++k) {
+            const uint32_t c = s_class[k];
+            s_class[k] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t q = a; q < b; ++q) qorder[atomicAdd(&s_class[size_class(nterms[q])], 1u)] = q;
+    __syncthreads();
+
+    // chunk prefix in that order
+    uint32_t sc = 0;
+    for (uint32_t p = a; p < b; ++p) sc += chunks_of(nterms[qorder[p]]);
+    uint32_t cbase = scan(sc);
+    for (uint32_t p = a; p < b; ++p) {
+        chunk_prefix[p] = cbase;
+        cbase += chunks_of(nterms[qorder[p]]);
+    }
     if (tid == nt - 1) {
-        chunk_prefix[n] = s_ch[nt - 1];
-        *total_items = (uint64_t)s_ch[nt - 1] * n_slices;
+        chunk_prefix[n] = cbase;
+        *total_items = (uint64_t)cbase * n_slices;
         *work_counter = 0;
         *cand_counter = 0;
     }
@@ -398,7 +432,6 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 {
     const uint32_t lane = lane_id();
     const uint64_t total = *a.total_items;
-    const uint32_t tchunks = a.chunk_prefix[a.n_queries];
     Counter<P> cnt;
 
     for (;;) {
@@ -406,10 +439,12 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
         if (lane == 0) item = atomicAdd(a.work_counter, 1ull);
         item = bcast64(item);
         if (item >= total) break;
-        const uint32_t sl = (uint32_t)(item / tchunks);
-        const uint32_t c = (uint32_t)(item - (uint64_t)sl * tchunks);
-        const uint32_t qi = bsearch_le(a.chunk_prefix, a.n_queries, c);
-        const uint32_t chunk = c - a.chunk_prefix[qi];
+        // items in query-size order, the slices of one chunk side by side
+        const uint32_t c = (uint32_t)(item / a.n_slices);
+        const uint32_t sl = (uint32_t)(item - (uint64_t)c * a.n_slices);
+        const uint32_t rank = bsearch_le(a.chunk_prefix, a.n_queries, c);
+        const uint32_t qi = a.qorder[rank];
+        const uint32_t chunk = c - a.chunk_prefix[rank];
         const QInfo qn = a.qinfo[qi];
         const SliceDesc sd = a.slices[sl];
         const uint32_t kbeg = chunk * a.chunk;
@@ -879,13 +914,13 @@ uint32_t dedup_groups(uint64_t windows)
 
 hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, const uint32_t *slot,
                        uint32_t n_queries, uint32_t chunk, uint32_t n_slices, uint32_t k_num,
-                       uint32_t k_den, uint64_t ell_limit, QInfo *qinfo, uint32_t *chunk_prefix,
-                       uint64_t *total_items, unsigned long long *work_counter,
-                       unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags,
-                       hipStream_t st)
+                       uint32_t k_den, uint64_t ell_limit, QInfo *qinfo, uint32_t *qorder,
+                       uint32_t *chunk_prefix, uint64_t *total_items,
+                       unsigned long long *work_counter, unsigned long long *cand_counter,
+                       uint32_t *qcount, uint32_t *flags, hipStream_t st)
 {
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, nterms, wbase, slot, n_queries, chunk,
-                       n_slices, k_num, k_den, ell_limit, qinfo, chunk_prefix, total_items,
+                       n_slices, k_num, k_den, ell_limit, qinfo, qorder, chunk_prefix, total_items,
                        work_counter, cand_counter, qcount, flags);
     return hipGetLastError();
 }

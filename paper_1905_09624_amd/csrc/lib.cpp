@@ -583,19 +583,16 @@ size_t batch_meta_bytes(uint32_t n)
             (size_t)n * 4 + 15) & ~size_t(15);
 }
 
-uint32_t auto_chunk(uint64_t W, uint32_t n, uint32_t n_slices, int grid)
+// Terms per work item: enough items to keep every resident wavefront busy
+// about four times over (items start largest first, so the last ones are
+// small), never more than cap (fewer, longer items; fewer merges) nor fewer
+// than 32 terms.
+uint32_t auto_chunk(uint64_t W, uint32_t n_slices, int grid, uint32_t cap)
 {
-    // enough work items to fill the persistent grid twice, chunks of <= 1024
-    // terms so that one long query does not leave a tail
     const uint64_t waves = (uint64_t)grid * 4;
-    const uint64_t base = (uint64_t)n * n_slices;
-    uint64_t c = 1024;
-    if (base < 2 * waves) {
-        const uint64_t want = 2 * waves - base;
-        c = (W * n_slices + want - 1) / want;
-    }
+    uint64_t c = (W * n_slices + 4 * waves - 1) / (4 * waves);
+    if (c > cap) c = cap;
     if (c < 32) c = 32;
-    if (c > 1024) c = 1024;
     return (uint32_t)c;
 }
 
@@ -650,17 +647,18 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     const int planes = gather_planes_for(maxw);
     int unroll = b.unroll ? (int)b.unroll : (ix->tuned_unroll ? ix->tuned_unroll : gather_default_unroll((int)h));
     if (!gather_unroll_valid(unroll, (int)h)) unroll = gather_default_unroll((int)h);
-    const int grid = gather_grid(planes, unroll, (int)h);
-    // a tuned chunk applies to batches that fill the persistent grid with one
-    // item per (query, slice); smaller batches split their queries instead
-    const bool fills = (uint64_t)n * n_slices >= 2ull * (uint64_t)grid * 4;
-    const uint32_t C = b.chunk ? b.chunk
-                               : (ix->tuned_chunk && fills ? ix->tuned_chunk : auto_chunk(W, n, n_slices, grid));
-    uint64_t pslots = 0;
+    int grid = gather_grid(planes, unroll, (int)h);
+    const uint32_t cap = b.chunk_cap ? b.chunk_cap : (ix->tuned_chunk ? ix->tuned_chunk : kDefaultChunkCap);
+    const uint32_t C = b.chunk ? b.chunk : auto_chunk(W, n_slices, grid, cap);
+    uint64_t pslots = 0, items = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t nw = wbase[i + 1] - wbase[i];
         if (nw > C) pslots += 1;   // may be split: one score buffer
+        items += (nw + C - 1) / C;
     }
+    // no more wavefronts than work items (4 per workgroup)
+    items *= n_slices;
+    if ((uint64_t)grid * 4 > items) grid = (int)std::max<uint64_t>(1, (items + 3) / 4);
     const TermSpec ts = term_spec(ix->prm);
 
     // uploads
@@ -720,6 +718,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     }
     COBS_HIP(ws.qinfo.ensure((size_t)n * sizeof(QInfo)));
     COBS_HIP(ws.chunk_prefix.ensure((size_t)(n + 1) * 4));
+    COBS_HIP(ws.qorder.ensure((size_t)n * 4));
     COBS_HIP(ws.scalars.ensure(sizeof(Scalars)));
     // score buffers of split queries: zero on allocation, left zero by every
     // complete gather launch
@@ -744,8 +743,9 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         COBS_HIP(ws.cand_q.ensure(ws.cand_cap * 4));
         COBS_HIP(launch_plan(ws.nterms.as<uint32_t>(), d_wbase, d_slot, n, C, n_slices,
                              b.k_num, b.k_den, ell_limit, ws.qinfo.as<QInfo>(),
-                             ws.chunk_prefix.as<uint32_t>(), &dsc->total_items, &dsc->work_counter,
-                             &dsc->cand_counter, ws.qcount.as<uint32_t>(), &dsc->flags, st));
+                             ws.qorder.as<uint32_t>(), ws.chunk_prefix.as<uint32_t>(),
+                             &dsc->total_items, &dsc->work_counter, &dsc->cand_counter,
+                             ws.qcount.as<uint32_t>(), &dsc->flags, st));
         if (full) {
             COBS_HIP(ws.full.ensure(std::max<uint64_t>((uint64_t)n * ix->n_docs, 1) * 4));
             COBS_HIP(hipMemsetAsync(ws.full.p, 0, (uint64_t)n * ix->n_docs * 4, st));
@@ -756,6 +756,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         ga.order = ix->d_order;
         ga.hashes = ws.hashes.as<uint64_t>();
         ga.qinfo = ws.qinfo.as<QInfo>();
+        ga.qorder = ws.qorder.as<uint32_t>();
         ga.chunk_prefix = ws.chunk_prefix.as<uint32_t>();
         ga.total_items = &dsc->total_items;
         ga.work_counter = &dsc->work_counter;
@@ -888,6 +889,7 @@ cobs_status reserve_workspace(cobs_index *ix, Workspace &ws, uint64_t W, uint32_
     }
     COBS_HIP(ws.qinfo.ensure((size_t)n * sizeof(QInfo)));
     COBS_HIP(ws.chunk_prefix.ensure((size_t)(n + 1) * 4));
+    COBS_HIP(ws.qorder.ensure((size_t)n * 4));
     COBS_HIP(ws.scalars.ensure(sizeof(Scalars)));
     COBS_HIP(ws.qcount.ensure((size_t)n * 4));
     ws.cand_cap = std::max<uint64_t>(ws.cand_cap, std::max<uint64_t>(1 << 20, (uint64_t)n * 64));
@@ -968,6 +970,7 @@ cobs_status query_driver(cobs_index *ix, const uint8_t *bytes, const uint64_t *q
     spec.k_den = opts->k_den;
     spec.topk = opts->topk;
     spec.score_bits = opts->score_bits;
+    spec.chunk = opts->chunk;
     cobs_status s = COBS_OK;
     BatchOut bo;
     if (opts->mode == COBS_MODE_BATCHED) {
@@ -1123,7 +1126,7 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
             spec.k_num = 1;
             spec.k_den = 1;
             spec.unroll = (uint32_t)u;
-            spec.chunk = c;
+            spec.chunk_cap = c;
             spec.time_gather = true;
             double t = 1e300;
             for (int rep = 0; rep < 2 && s == COBS_OK; ++rep) {   // first run warms up

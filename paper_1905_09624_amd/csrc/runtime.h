@@ -57,7 +57,7 @@ struct Block {
 // Everything one query batch needs on the device; reused across batches.
 struct Workspace {
     DevBuf bytes, meta, terms, uterms, hashes, nterms, table;
-    DevBuf tickets, qinfo, chunk_prefix, scalars, accum;
+    DevBuf tickets, qinfo, qorder, chunk_prefix, scalars, accum;
     DevBuf cand_key, cand_q, qcount, gstart, gcursor, seg_a, seg_b;
     DevBuf out_start, out_n, out_id, out_score, full;
     HostBuf h_stage, h_small, h_out;
@@ -84,7 +84,8 @@ struct BatchSpec {
     uint32_t n = 0;
     uint32_t mem = COBS_MEM_HOST;
     uint32_t k_num = 0, k_den = 1, topk = 0, score_bits = 32;
-    uint32_t chunk = 0;                // terms per work item; 0 = tuned or automatic
+    uint32_t chunk = 0;                // terms per work item; 0 = automatic
+    uint32_t chunk_cap = 0;            // automatic chunk's maximum; 0 = tuned or kDefaultChunkCap
     uint32_t unroll = 0;               // terms in flight per wavefront; 0 = tuned or default
     uint32_t *full_scores = nullptr;   // host [n * n_docs]: full score mode
     uint64_t *terms_out = nullptr;     // host [windows]: terms-only mode

@@ -251,24 +251,55 @@ def test_long_query_multi_chunk_and_global_table():
         assert np.array_equal(sc[i], want)
     check_queries(gix, oix, data, off, k=(1, 5), topk=0, mode=0)
     check_queries(gix, oix, data, off, k=(0, 1), topk=7, mode=1)
+    # each query in a single work item (no merge) and in many small ones
+    for chunk in (1 << 20, 300):
+        res = gix.query(data, off, k=(1, 5), chunk=chunk)
+        for i, s in enumerate(qs):
+            ids, sc, l = oix.query(s, 1, 5, 0)
+            assert res[i][2] == l and np.array_equal(res[i][0], ids) and np.array_equal(res[i][1], sc)
 
 
-@pytest.mark.parametrize("unroll,chunk", [(4, 32), (8, 100), (4, 1024), (8, 7)])
+@pytest.mark.parametrize("unroll,chunk", [(4, 32), (8, 100), (4, 1024), (8, 7), (8, 1 << 20)])
 def test_launch_shapes_give_identical_results(workload, unroll, chunk):
-    # every instantiated unroll and several term-chunk sizes (many partial
-    # merges at chunk 7) give the oracle's scores and hits
+    # every instantiated unroll and several term-chunk sizes (many merges at
+    # chunk 7, every query in one work item at 2^20) give the oracle's scores
+    # (K = 0 reports every document with its score) and hits
     w, d, qs, gix, oix = workload
     if w.h > 1:
         unroll //= 2
-    gix.set_tuning(unroll, chunk)
+    gix.set_tuning(unroll, 0)
     try:
-        sc, l = gix.scores(qs.bytes, qs.q_off)
+        res = gix.query(qs.bytes, qs.q_off, k=(0, 1), chunk=chunk)
         for i in range(qs.n):
             want, wl = oix.query_scores(qs.get(i))
-            assert l[i] == wl and np.array_equal(sc[i], want), (unroll, chunk, i)
-        check_queries(gix, oix, qs.bytes, qs.q_off, k=(1, 2), topk=4, mode=0)
+            ids, sc, l = res[i]
+            assert l == wl, (unroll, chunk, i)
+            full = np.zeros_like(want)
+            full[ids] = sc
+            assert len(ids) == (len(want) if wl else 0)
+            if wl:
+                assert np.array_equal(full, want), (unroll, chunk, i)
+        res = gix.query(qs.bytes, qs.q_off, k=(1, 2), topk=4, chunk=chunk)
+        for i in range(qs.n):
+            ids, sc, l = oix.query(qs.get(i), 1, 2, 4)
+            assert res[i][2] == l and np.array_equal(res[i][0], ids), (unroll, chunk, i)
+            assert np.array_equal(res[i][1], sc), (unroll, chunk, i)
     finally:
         gix.set_tuning(0, 0)
+
+
+def test_tuned_chunk_caps_the_split(workload):
+    # a tuned chunk is the largest work item; any cap gives the same hits
+    w, d, qs, gix, oix = workload
+    base = gix.query(qs.bytes, qs.q_off, k=(1, 2))
+    for cap in (7, 64, 1 << 20):
+        gix.set_tuning(0, cap)
+        try:
+            got = gix.query(qs.bytes, qs.q_off, k=(1, 2))
+        finally:
+            gix.set_tuning(0, 0)
+        for x, y in zip(base, got):
+            assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
 
 
 def test_autotune_keeps_results(workload):
