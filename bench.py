@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk-gb", type=float, default=8.0,
                     help="device bytes of documents generated per build run")
-    ap.add_argument("--serve-rates", type=str, default="1000,7100",
+    ap.add_argument("--serve-rates", type=str, default="1000,2700,7100,18800,50000",
                     help="Poisson arrival rates (q/s) of the serving measurement; '' skips it")
     ap.add_argument("--serve-pool", type=int, default=1000)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -158,19 +158,26 @@ def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, pl
     bt = time.perf_counter() - t1
     out["one_batch"] = {"queries_per_s": pool_n / bt, "lookups_per_s": float(nt.sum()) / bt,
                         "seconds": bt}
-    for rate in rates:
-        n = int(min(max_req, max(rate * per_rate_s, 200)))
+    def replay(n, rate, **opts):
         idx = np.arange(n) % pool_n
         q = pool.subset(idx) if n != pool_n else pool
         arr = synth.arrivals(0x5E7E + int(rate), n, float(rate))
-        srv = cobs.Server(ix, num_streams=4)
-        lat_ns, nh = srv.replay(q.bytes, q.q_off, arr, k=k)
+        srv = cobs.Server(ix, **opts)
+        srv.replay(q.bytes, q.q_off, arr, k=k)
         st = srv.stop()
-        rec = {"rate_qps": rate, "requests": n, "completed": int(st["completed"]),
-               "batches": int(st["batches"]), "p50_ms": st["p50_ns"] / 1e6,
-               "p99_ms": st["p99_ns"] / 1e6, "max_ms": st["max_ns"] / 1e6,
-               "queries_per_s": st["queries_per_s"], "lookups_per_s": st["lookups_per_s"],
-               "vs_plain_throughput": st["queries_per_s"] / plain["queries_per_s"]}
+        return {"requests": n, "completed": int(st["completed"]),
+                "batches": int(st["batches"]), "p50_ms": st["p50_ns"] / 1e6,
+                "p99_ms": st["p99_ns"] / 1e6, "max_ms": st["max_ns"] / 1e6,
+                "queries_per_s": st["queries_per_s"], "lookups_per_s": st["lookups_per_s"]}
+
+    for rate in rates:
+        n = int(min(max_req, max(rate * per_rate_s, 200)))
+        rec = {"rate_qps": rate, **replay(n, rate, num_streams=4)}
+        rec["vs_plain_throughput"] = rec["queries_per_s"] / plain["queries_per_s"]
+        # the plain path served: one query per launch, first come first served;
+        # beyond its capacity the queue only grows, so fewer requests are sent
+        n_p = int(min(n, max(200, 2 * plain["queries_per_s"])))
+        rec["plain_served"] = replay(n_p, rate, num_streams=1, max_batch_queries=1)
         out["rates"].append(rec)
         log(f"serving at {rate} q/s: {rec}")
     return out

@@ -316,7 +316,7 @@ cobs_status cobs_serve_replay(cobs_server *s, const uint8_t *bytes, const uint64
  * Launch shape of the gather kernel for an index: `unroll` terms whose rows
  * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4) and `chunk`,
  * the most distinct terms per work item (longer queries are split and their
- * counts merged; a batch is split into about four work items per resident
+ * counts merged; a batch is split into about two work items per resident
  * wavefront, with items of at most `chunk` terms).  0 = defaults (8 or 2;
  * 16384).  Results never depend on either.
  */

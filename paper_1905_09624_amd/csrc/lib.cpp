@@ -584,13 +584,13 @@ size_t batch_meta_bytes(uint32_t n)
 }
 
 // Terms per work item: enough items to keep every resident wavefront busy
-// about four times over (items start largest first, so the last ones are
-// small), never more than cap (fewer, longer items; fewer merges) nor fewer
-// than 32 terms.
+// about twice over (items start largest first, so the last ones are small),
+// never more than cap (fewer, longer items; fewer merges) nor fewer than 32
+// terms.
 uint32_t auto_chunk(uint64_t W, uint32_t n_slices, int grid, uint32_t cap)
 {
     const uint64_t waves = (uint64_t)grid * 4;
-    uint64_t c = (W * n_slices + 4 * waves - 1) / (4 * waves);
+    uint64_t c = (W * n_slices + 2 * waves - 1) / (2 * waves);
     if (c > cap) c = cap;
     if (c < 32) c = 32;
     return (uint32_t)c;
