@@ -500,43 +500,85 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
         }
 
         // Several chunks of one (query, slice): each adds its counts into the
-        // query's score buffer (device-scope atomics; document (lane, d, bit)
-        // at (d*32 + bit)*lanes + lane, so one instruction's lanes touch
-        // consecutive words); the last chunk to finish reads the totals back
-        // into bit planes and clears the buffer for the next batch.  The cost
-        // of the merge does not grow with the number of chunks.  Lanes past
-        // the slice's documents hold zero counts and touch nothing.
+        // query's score buffer with device-scope atomic adds, then takes a
+        // ticket; the last chunk to finish reads the totals back into bit
+        // planes, clears the buffer for the next batch and reports.  The merge
+        // costs the same for 2 chunks or 2,000.  Layout per slice: document
+        // (lane, d, bit) at (d*32 + bit)*lanes + lane, or, while l < 2^16 (no
+        // count can pass 16 bits), four documents (bit, bit+8, bit+16, bit+24)
+        // in one 64-bit word at (d*8 + bit)*lanes + lane; either way one
+        // instruction's lanes touch consecutive words.  Lanes past the slice's
+        // documents hold zero counts and touch nothing.  Every access to the
+        // buffer and the tickets is a device-scope atomic, so ordering needs
+        // only the wait for this wavefront's adds before its ticket (no cache
+        // write-back or invalidation).
         if (qn.nch > 1) {
             const uint32_t L = uniform_u32(sd.lanes);
             uint32_t *acc = a.accum + (uint64_t)qn.pbase * a.acc_words + uniform_u32(sd.acc_off);
+            unsigned long long *acc4 = (unsigned long long *)acc;
+            const bool packed = qn.ell < 65536u;
+            if (packed) {
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-#pragma unroll 4
-                for (int bit = 0; bit < 32; ++bit) {
-                    const uint32_t c = cnt.score(d, bit);
-                    if (c)
-                        __hip_atomic_fetch_add(acc + (d * 32 + bit) * L + lane, c, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                for (int d = 0; d < 4; ++d) {
+#pragma unroll 2
+                    for (int b = 0; b < 8; ++b) {
+                        const unsigned long long v =
+                            (unsigned long long)cnt.score(d, b) |
+                            ((unsigned long long)cnt.score(d, b + 8) << 16) |
+                            ((unsigned long long)cnt.score(d, b + 16) << 32) |
+                            ((unsigned long long)cnt.score(d, b + 24) << 48);
+                        if (v)
+                            __hip_atomic_fetch_add(acc4 + (d * 8 + b) * L + lane, v, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
-            }
-            __threadfence();
-            uint32_t tk = 0;
-            if (lane == 0) tk = atomicAdd(&a.tickets[(uint64_t)qi * a.n_slices + sl], 1u);
-            tk = uniform_u32(tk);
-            if (tk != qn.nch - 1) continue;
-            __threadfence();
-            if (lane == 0) a.tickets[(uint64_t)qi * a.n_slices + sl] = 0;   // ready for reuse
-            cnt.clear();
-            if (lane < L) {
+            } else {
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
 #pragma unroll 4
                     for (int bit = 0; bit < 32; ++bit) {
-                        uint32_t *cell = acc + (d * 32 + bit) * L + lane;
-                        const uint32_t c = __hip_atomic_load(cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        *cell = 0;
+                        const uint32_t c = cnt.score(d, bit);
+                        if (c)
+                            __hip_atomic_fetch_add(acc + (d * 32 + bit) * L + lane, c, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
+            __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");   // adds done before the ticket
+            uint32_t *ticket = &a.tickets[(uint64_t)qi * a.n_slices + sl];
+            uint32_t tk = 0;
+            if (lane == 0) tk = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tk = uniform_u32(tk);
+            if (tk != qn.nch - 1) continue;
+            if (lane == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            cnt.clear();
+            if (lane < L) {
+                if (packed) {
 #pragma unroll
-                        for (int p = 0; p < P; ++p) cnt.H[p][d] |= ((c >> p) & 1u) << bit;
+                    for (int d = 0; d < 4; ++d) {
+#pragma unroll 2
+                        for (int b = 0; b < 8; ++b) {
+                            unsigned long long *cell = acc4 + (d * 8 + b) * L + lane;
+                            const unsigned long long v =
+                                __hip_atomic_exchange(cell, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const uint32_t c = (uint32_t)(v >> (16 * j)) & 0xFFFFu;
+#pragma unroll
+                                for (int p = 0; p < P; ++p) cnt.H[p][d] |= ((c >> p) & 1u) << (b + 8 * j);
+                            }
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+#pragma unroll 4
+                        for (int bit = 0; bit < 32; ++bit) {
+                            const uint32_t c = __hip_atomic_exchange(acc + (d * 32 + bit) * L + lane, 0u,
+                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                            for (int p = 0; p < P; ++p) cnt.H[p][d] |= ((c >> p) & 1u) << bit;
+                        }
                     }
                 }
             }
