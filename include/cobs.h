@@ -142,9 +142,30 @@ typedef struct {
                                document, each 8192-document slice rounded up
                                to whole 128-document lanes (the unit by which
                                cobs_serve admits requests) */
+    uint32_t host_resident; /* 1 after cobs_index_offload */
+    uint32_t n_groups;      /* block groups streamed per batch when offloaded */
+    uint64_t stage_bytes;   /* size of each of the two device staging buffers */
 } cobs_index_info_t;
 
 cobs_status cobs_index_info(const cobs_index *ix, cobs_index_info_t *info);
+
+/*
+ * Out-of-core queries (section 2.3 and section 4: an index need not fit in
+ * memory; blocks are read as they are needed).  cobs_index_offload moves the
+ * signature matrix into pinned host memory and frees its device memory; every
+ * later query batch streams the matrix through two device staging buffers,
+ * each of at most device_budget_bytes / 2 and holding a group of whole
+ * consecutive blocks: the copy of one group (DMA over the host link) overlaps
+ * the gather of the previous one.  A batch therefore reads the whole matrix
+ * once over the host link, and large batches amortise it.  Results are
+ * identical.  Batches on an offloaded index run one at a time.
+ * cobs_index_onload moves the matrix back into device memory.  Neither may
+ * run while another thread queries the index.
+ * Errors: EBUDGET when half the budget cannot hold the largest block;
+ * ESTATE when the matrix already is where it would be moved; ENOMEM; EDEVICE.
+ */
+cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes);
+cobs_status cobs_index_onload(cobs_index *ix);
 /* Block b: first sorted position, documents, rows m_b, row stride (bytes),
  * byte offset of the block inside the matrix. */
 cobs_status cobs_index_block(const cobs_index *ix, uint32_t b, uint32_t *first,

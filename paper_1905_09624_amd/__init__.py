@@ -43,7 +43,9 @@ class DocsC(C.Structure):
 
 class IndexInfo(C.Structure):
     _fields_ = [("n_docs", C.c_uint32), ("n_blocks", C.c_uint32), ("params", Params),
-                ("total_bytes", C.c_uint64), ("score_bytes", C.c_uint64)]
+                ("total_bytes", C.c_uint64), ("score_bytes", C.c_uint64),
+                ("host_resident", C.c_uint32), ("n_groups", C.c_uint32),
+                ("stage_bytes", C.c_uint64)]
 
 
 class QueryOpts(C.Structure):
@@ -94,6 +96,8 @@ EXPORTS = {
                                    C.c_void_p, C.c_void_p]),
     "cobs_index_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cobs_index_read": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p]),
+    "cobs_index_offload": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "cobs_index_onload": (C.c_int, [C.c_void_p]),
     "cobs_query_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
                                    C.POINTER(QueryOpts), C.c_void_p, C.POINTER(C.POINTER(Hits))]),
     "cobs_query_scores": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
@@ -239,7 +243,16 @@ class Index:
         i = IndexInfo()
         _check(lib().cobs_index_info(self._h, C.byref(i)))
         return dict(n_docs=i.n_docs, n_blocks=i.n_blocks, total_bytes=i.total_bytes,
-                    score_bytes=i.score_bytes)
+                    score_bytes=i.score_bytes, host_resident=bool(i.host_resident),
+                    n_groups=i.n_groups, stage_bytes=i.stage_bytes)
+
+    def offload(self, device_budget_bytes: int) -> None:
+        """Matrix to pinned host memory; queries stream it (cobs_index_offload)."""
+        _check(lib().cobs_index_offload(self._h, device_budget_bytes))
+
+    def onload(self) -> None:
+        """Matrix back into device memory (cobs_index_onload)."""
+        _check(lib().cobs_index_onload(self._h))
 
     def block(self, b: int) -> dict:
         f, d = C.c_uint32(), C.c_uint32()

@@ -41,9 +41,7 @@ struct SliceDesc {
 };
 
 // Score buffer of one query (split queries only): for each slice, 128 * lanes
-// words, document (lane, d, bit) of the slice at acc_off + (d*32 + bit)*lanes
-// + lane; n_docs + 127 * n_slices words at most.
-uint64_t score_buffer_words(const SliceDesc *slices, uint32_t n_slices);
+// words from acc_off on; n_docs + 127 * n_slices words at most.
 
 // Per-query state filled by the plan kernel.
 struct QInfo {
@@ -79,8 +77,7 @@ struct GatherArgs {
     const QInfo *qinfo;
     const uint32_t *qorder;            // [n_queries] work order of the queries
     const uint32_t *chunk_prefix;      // [n_queries + 1], in qorder order
-    const uint64_t *total_items;       // device scalar
-    unsigned long long *work_counter;  // device scalar
+    unsigned long long *work_counter;  // device scalar, zero at launch; items = chunks x n_slices
     uint32_t *tickets;                 // [n_queries * n_slices]
     uint32_t *accum;                   // score buffers of split queries (zero between launches)
     uint64_t acc_words;                // words per score buffer

@@ -436,7 +436,7 @@ template <int P, int U, bool kH1>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 {
     const uint32_t lane = lane_id();
-    const uint64_t total = *a.total_items;
+    const uint64_t total = (uint64_t)a.chunk_prefix[a.n_queries] * a.n_slices;
     Counter<P> cnt;
 
     for (;;) {
@@ -938,13 +938,6 @@ hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint
     hipLaunchKernelGGL(dedup_kernel, dim3(n_groups), dim3(256), 0, st, terms, wbase, tbase,
                        bprefix, n_queries, table, uterms, hashes, nterms, ts, seeds);
     return hipGetLastError();
-}
-
-uint64_t score_buffer_words(const SliceDesc *slices, uint32_t n_slices)
-{
-    uint64_t w = 0;
-    for (uint32_t i = 0; i < n_slices; ++i) w += 128ull * slices[i].lanes;
-    return w;
 }
 
 uint64_t dedup_table_slots(uint64_t windows)

@@ -152,9 +152,29 @@ static uint64_t filter_rows(uint64_t n, uint32_t h, double p)
 
 using namespace cobs;
 
+void cobs_index::release_offload()
+{
+    for (int i = 0; i < 2; ++i) {
+        if (d_stage[i]) (void)hipFree(d_stage[i]);
+        if (ev_copy[i]) (void)hipEventDestroy(ev_copy[i]);
+        if (ev_done[i]) (void)hipEventDestroy(ev_done[i]);
+        d_stage[i] = nullptr;
+        ev_copy[i] = ev_done[i] = nullptr;
+    }
+    if (copy_stream) (void)hipStreamDestroy(copy_stream);
+    if (d_group_slices) (void)hipFree(d_group_slices);
+    if (h_matrix) (void)hipHostFree(h_matrix);
+    copy_stream = nullptr;
+    d_group_slices = nullptr;
+    h_matrix = nullptr;
+    groups.clear();
+    stage_bytes = 0;
+}
+
 cobs_index::~cobs_index()
 {
     for (Workspace *w : pool) delete w;
+    release_offload();
     if (d_matrix) (void)hipFree(d_matrix);
     if (d_order) (void)hipFree(d_order);
     if (d_slices) (void)hipFree(d_slices);
@@ -510,6 +530,9 @@ cobs_status cobs_index_info(const cobs_index *ix, cobs_index_info_t *info)
     info->params = ix->prm;
     info->total_bytes = ix->total_bytes;
     info->score_bytes = ix->acc_words * 4;
+    info->host_resident = ix->h_matrix ? 1 : 0;
+    info->stage_bytes = ix->stage_bytes;
+    info->n_groups = (uint32_t)ix->groups.size();
     return COBS_OK;
 }
 
@@ -540,7 +563,99 @@ cobs_status cobs_index_read(const cobs_index *ix, uint64_t offset, uint64_t nbyt
     if (!ix || (!dst && nbytes)) return set_error(COBS_EINVAL, "NULL argument");
     if (offset > ix->total_bytes || nbytes > ix->total_bytes - offset)
         return set_error(COBS_EINVAL, "range outside the matrix");
-    if (nbytes) COBS_HIP(hipMemcpy(dst, ix->d_matrix + offset, nbytes, hipMemcpyDeviceToHost));
+    if (!nbytes) return COBS_OK;
+    if (ix->h_matrix)
+        std::memcpy(dst, ix->h_matrix + offset, nbytes);
+    else
+        COBS_HIP(hipMemcpy(dst, ix->d_matrix + offset, nbytes, hipMemcpyDeviceToHost));
+    return COBS_OK;
+}
+
+cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes)
+{
+    if (!ix) return set_error(COBS_EINVAL, "index is NULL");
+    std::lock_guard<std::mutex> g(ix->stream_mu);
+    if (ix->h_matrix) return set_error(COBS_ESTATE, "the matrix is already in host memory");
+    (void)hipSetDevice(ix->device);
+    const uint64_t half = device_budget_bytes / 2 & ~uint64_t(255);
+    // groups of whole consecutive blocks, each within one staging buffer
+    std::vector<cobs_index::Group> groups;
+    uint32_t s0 = 0;
+    for (size_t b = 0; b < ix->blocks.size(); ++b) {
+        const Block &blk = ix->blocks[b];
+        const uint64_t end = blk.offset + blk.rows * blk.stride;
+        uint32_t ns = 0;
+        while (s0 + ns < ix->slices.size() && ix->slices[s0 + ns].block == b) ++ns;
+        if (end - blk.offset > half)
+            return set_error(COBS_EBUDGET, "half the device budget must hold the largest block (" +
+                                                std::to_string(end - blk.offset) + " bytes)");
+        if (!groups.empty() && end - groups.back().off <= half) {
+            groups.back().bytes = end - groups.back().off;
+            groups.back().n_slices += ns;
+        } else {
+            groups.push_back(cobs_index::Group{s0, ns, blk.offset, end - blk.offset});
+        }
+        s0 += ns;
+    }
+    uint64_t stage = 0;
+    for (const auto &gr : groups) stage = std::max(stage, gr.bytes);
+    std::vector<SliceDesc> rebased = ix->slices;
+    for (const auto &gr : groups)
+        for (uint32_t i = 0; i < gr.n_slices; ++i) rebased[gr.slice0 + i].base -= gr.off;
+    auto fail = [&](cobs_status st) {
+        ix->release_offload();
+        return st;
+    };
+    hipError_t e = hipHostMalloc((void **)&ix->h_matrix, std::max<uint64_t>(ix->total_bytes, 1));
+    if (e != hipSuccess) {
+        ix->h_matrix = nullptr;
+        return fail(set_error(COBS_ENOMEM, "pinned host memory for the matrix"));
+    }
+    if (ix->total_bytes)
+        if ((e = hipMemcpy(ix->h_matrix, ix->d_matrix, ix->total_bytes, hipMemcpyDeviceToHost)) != hipSuccess)
+            return fail(hip_error(e, "hipMemcpy(matrix to host)"));
+    for (int i = 0; i < 2; ++i) {
+        if (stage && (e = hipMalloc(&ix->d_stage[i], stage)) != hipSuccess) {
+            ix->d_stage[i] = nullptr;
+            return fail(hip_error(e, "hipMalloc(staging)"));
+        }
+        if ((e = hipEventCreateWithFlags(&ix->ev_copy[i], hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ix->ev_done[i], hipEventDisableTiming)) != hipSuccess)
+            return fail(hip_error(e, "hipEventCreate"));
+    }
+    if ((e = hipStreamCreateWithFlags(&ix->copy_stream, hipStreamNonBlocking)) != hipSuccess)
+        return fail(hip_error(e, "hipStreamCreate"));
+    if ((e = hipMalloc(&ix->d_group_slices, std::max<size_t>(rebased.size(), 1) * sizeof(SliceDesc))) !=
+        hipSuccess) {
+        ix->d_group_slices = nullptr;
+        return fail(hip_error(e, "hipMalloc(slices)"));
+    }
+    if (!rebased.empty() &&
+        (e = hipMemcpy(ix->d_group_slices, rebased.data(), rebased.size() * sizeof(SliceDesc),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_error(e, "hipMemcpy(slices)"));
+    ix->groups = groups;
+    ix->stage_bytes = stage;
+    if (ix->d_matrix) (void)hipFree(ix->d_matrix);
+    ix->d_matrix = nullptr;
+    return COBS_OK;
+}
+
+cobs_status cobs_index_onload(cobs_index *ix)
+{
+    if (!ix) return set_error(COBS_EINVAL, "index is NULL");
+    std::lock_guard<std::mutex> g(ix->stream_mu);
+    if (!ix->h_matrix) return set_error(COBS_ESTATE, "the matrix is already in device memory");
+    (void)hipSetDevice(ix->device);
+    uint8_t *d = nullptr;
+    hipError_t e = hipMalloc(&d, std::max<uint64_t>(ix->total_bytes, 1));
+    if (e != hipSuccess) return set_error(COBS_ENOMEM, "device memory for the matrix");
+    if (ix->total_bytes && (e = hipMemcpy(d, ix->h_matrix, ix->total_bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(d);
+        return hip_error(e, "hipMemcpy(matrix to device)");
+    }
+    ix->d_matrix = d;
+    ix->release_offload();
     return COBS_OK;
 }
 
@@ -598,9 +713,55 @@ uint32_t auto_chunk(uint64_t W, uint32_t n_slices, int grid, uint32_t cap)
 
 }  // namespace
 
+// The gather of an offloaded index: group by group, the copy of group g + 2
+// (on the index's copy stream) overlaps the gathers of groups g and g + 1 (on
+// st), through two staging buffers.  The caller holds ix->stream_mu.
+static cobs_status gather_streamed(cobs_index *ix, Workspace &ws, GatherArgs ga, int planes, int unroll,
+                                   int grid, hipStream_t st)
+{
+    const size_t G = ix->groups.size();
+    COBS_HIP(ws.counters.ensure(G * 8));
+    unsigned long long *counters = ws.counters.as<unsigned long long>();
+    COBS_HIP(launch_fill_u64((uint64_t *)counters, G, 0, st));
+    // the copies start after everything before them on st (earlier batches
+    // read the staging buffers)
+    COBS_HIP(hipEventRecord(ix->ev_done[0], st));
+    COBS_HIP(hipEventRecord(ix->ev_done[1], st));
+    auto copy = [&](size_t g) -> cobs_status {
+        const cobs_index::Group &gr = ix->groups[g];
+        COBS_HIP(hipStreamWaitEvent(ix->copy_stream, ix->ev_done[g % 2], 0));
+        COBS_HIP(hipMemcpyAsync(ix->d_stage[g % 2], ix->h_matrix + gr.off, gr.bytes,
+                                hipMemcpyHostToDevice, ix->copy_stream));
+        COBS_HIP(hipEventRecord(ix->ev_copy[g % 2], ix->copy_stream));
+        return COBS_OK;
+    };
+    for (size_t g = 0; g < std::min<size_t>(G, 2); ++g) {
+        cobs_status c = copy(g);
+        if (c != COBS_OK) return c;
+    }
+    for (size_t g = 0; g < G; ++g) {
+        const cobs_index::Group &gr = ix->groups[g];
+        COBS_HIP(hipStreamWaitEvent(st, ix->ev_copy[g % 2], 0));
+        GatherArgs a = ga;
+        a.matrix = ix->d_stage[g % 2];
+        a.slices = ix->d_group_slices + gr.slice0;
+        a.n_slices = gr.n_slices;
+        a.work_counter = counters + g;
+        COBS_HIP(launch_gather(a, planes, unroll, grid, st));
+        COBS_HIP(hipEventRecord(ix->ev_done[g % 2], st));
+        if (g + 2 < G) {
+            cobs_status c = copy(g + 2);
+            if (c != COBS_OK) return c;
+        }
+    }
+    return COBS_OK;
+}
+
 cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStream_t st,
                       BatchOut &out)
 {
+    std::unique_lock<std::mutex> streaming(ix->stream_mu, std::defer_lock);
+    if (ix->h_matrix) streaming.lock();   // one streamed batch at a time
     const uint32_t n = b.n;
     out.num_terms.assign(n, 0);
     out.n.assign(n, 0);
@@ -758,7 +919,6 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         ga.qinfo = ws.qinfo.as<QInfo>();
         ga.qorder = ws.qorder.as<uint32_t>();
         ga.chunk_prefix = ws.chunk_prefix.as<uint32_t>();
-        ga.total_items = &dsc->total_items;
         ga.work_counter = &dsc->work_counter;
         ga.tickets = ws.tickets.as<uint32_t>();
         ga.accum = accum;
@@ -782,7 +942,11 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
                 if (!e) COBS_HIP(hipEventCreate(&e));
             COBS_HIP(hipEventRecord(ws.ev[0], st));
         }
-        if (n_slices) COBS_HIP(launch_gather(ga, planes, unroll, grid, st));
+        if (n_slices && !ix->h_matrix) COBS_HIP(launch_gather(ga, planes, unroll, grid, st));
+        if (n_slices && ix->h_matrix) {
+            cobs_status gs = gather_streamed(ix, ws, ga, planes, unroll, grid, st);
+            if (gs != COBS_OK) return gs;
+        }
         if (timed) COBS_HIP(hipEventRecord(ws.ev[1], st));
         auto account = [&](const uint32_t *nt) -> cobs_status {
             if (!timed) return COBS_OK;

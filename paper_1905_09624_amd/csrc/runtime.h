@@ -58,7 +58,7 @@ struct Block {
 struct Workspace {
     DevBuf bytes, meta, terms, uterms, hashes, nterms, table;
     DevBuf tickets, qinfo, qorder, chunk_prefix, scalars, accum;
-    DevBuf cand_key, cand_q, qcount, gstart, gcursor, seg_a, seg_b;
+    DevBuf cand_key, cand_q, qcount, gstart, gcursor, seg_a, seg_b, counters;
     DevBuf out_start, out_n, out_id, out_score, full;
     HostBuf h_stage, h_small, h_out;
     uint64_t tickets_slots = 0;
@@ -114,6 +114,24 @@ struct cobs_index {
     uint64_t acc_words = 0;            // words of one query's score buffer
     std::mutex pool_mu;
     std::vector<cobs::Workspace *> pool;
+
+    // Out-of-core residency (cobs_index_offload): the matrix in pinned host
+    // memory, streamed group by group (whole blocks) through two device
+    // staging buffers; one streamed batch at a time.
+    struct Group {
+        uint32_t slice0, n_slices;   // slices of the group's blocks
+        uint64_t off, bytes;         // byte range of the matrix
+    };
+    uint8_t *h_matrix = nullptr;
+    std::vector<Group> groups;
+    cobs::SliceDesc *d_group_slices = nullptr;   // slices, base relative to their group
+    uint8_t *d_stage[2] = {nullptr, nullptr};
+    uint64_t stage_bytes = 0;
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_copy[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
+    std::mutex stream_mu;
+
+    void release_offload();
     ~cobs_index();
 };
 
