@@ -165,6 +165,30 @@ cobs_status cobs_index_info(const cobs_index *ix, cobs_index_info_t *info);
  * ESTATE when the matrix already is where it would be moved; ENOMEM; EDEVICE.
  */
 cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes);
+
+/*
+ * Index files (section 2.3: an index is written once and queried many times,
+ * read into memory or as needed).  One file per index, little-endian:
+ *   header    "COBSMTX1", header size (u32), kind, q, canonical, num_hashes,
+ *             block_docs (u32 each), fpr (f64), seed (u64), n_docs, n_blocks
+ *             (u32), total_bytes, matrix offset, metadata FNV-1a 64 (u64)
+ *   order     u32[n_docs]   sorted position -> input id
+ *   n_terms   u64[n_docs]   distinct terms per input id
+ *   blocks    {first u32, docs u32, rows u64, stride u64, offset u64}[n_blocks]
+ *   padding   to a multiple of 4096 bytes
+ *   matrix    total_bytes: the blocks one after another, each at its offset,
+ *             rows of stride bytes, document j of a block at bit j % 8 of
+ *             byte j / 8 (the device layout)
+ * cobs_index_load checks the magic, the parameters, the checksum and that
+ * the order and block table follow from the stored counts (EINVAL
+ * otherwise).  device_budget_bytes = 0 puts the matrix in device memory of
+ * `device`; otherwise it stays in pinned host memory and queries stream it as
+ * after cobs_index_offload with that budget.  The caller owns *out
+ * (cobs_index_free).  Errors: EINVAL (I/O, format), EBUDGET, ENOMEM, EDEVICE.
+ */
+cobs_status cobs_index_save(const cobs_index *ix, const char *path);
+cobs_status cobs_index_load(const char *path, int device, uint64_t device_budget_bytes,
+                            cobs_index **out);
 cobs_status cobs_index_onload(cobs_index *ix);
 /* Block b: first sorted position, documents, rows m_b, row stride (bytes),
  * byte offset of the block inside the matrix. */

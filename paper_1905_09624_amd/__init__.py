@@ -96,6 +96,8 @@ EXPORTS = {
                                    C.c_void_p, C.c_void_p]),
     "cobs_index_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cobs_index_read": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p]),
+    "cobs_index_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "cobs_index_load": (C.c_int, [C.c_char_p, C.c_int, C.c_uint64, C.POINTER(C.c_void_p)]),
     "cobs_index_offload": (C.c_int, [C.c_void_p, C.c_uint64]),
     "cobs_index_onload": (C.c_int, [C.c_void_p]),
     "cobs_query_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
@@ -194,7 +196,8 @@ def make_params(kind=DNA, q=31, canonical=True, h=1, p=0.3, B=0, seed=0x5EED) ->
 
 
 class Index:
-    """A COBS index resident in HBM of the current device."""
+    """A COBS index: the matrix in HBM of its device, or in pinned host memory
+    after offload (streamed per query batch)."""
 
     def __init__(self, handle):
         self._h = handle
@@ -205,6 +208,18 @@ class Index:
         h = C.c_void_p()
         _check(lib().cobs_build(C.byref(params), C.byref(d), _stream(stream), C.byref(h)))
         return cls(h)
+
+    @classmethod
+    def load(cls, path: str, device: int = 0, device_budget_bytes: int = 0) -> "Index":
+        """Index from a file written by save (cobs_index_load); a non-zero
+        budget keeps the matrix in host memory, streamed per batch."""
+        h = C.c_void_p()
+        _check(lib().cobs_index_load(os.fsencode(path), device, device_budget_bytes, C.byref(h)))
+        return cls(h)
+
+    def save(self, path: str) -> None:
+        """Write the index to a file (cobs_index_save)."""
+        _check(lib().cobs_index_save(self._h, os.fsencode(path)))
 
     @classmethod
     def build_streamed(cls, params: Params, n_docs: int, runs, stream=None) -> "Index":

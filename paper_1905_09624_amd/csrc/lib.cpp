@@ -10,8 +10,10 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <ctime>
+#include <memory>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -376,27 +378,26 @@ cobs_status cobs_builder_count(cobs_builder *b, const cobs_docs *run, uint32_t f
     return COBS_OK;
 }
 
-cobs_status cobs_builder_plan(cobs_builder *b)
+namespace {
+
+// The index layout from the documents' distinct-term counts (ix->prm,
+// n_docs, n_terms set): compact order sorted by (distinct terms, input id)
+// (sections 2.2, 2.3), blocks with their row counts, padded rows, column
+// slices and score-buffer offsets.  Host only.
+cobs_status make_layout(cobs_index *ix)
 {
-    if (!b) return set_error(COBS_EINVAL, "builder is NULL");
-    if (b->state != 0) return set_error(COBS_ESTATE, "plan called twice");
-    for (uint32_t d = 0; d < b->n_docs; ++d)
-        if (!b->counted[d]) return set_error(COBS_ESTATE, "document " + std::to_string(d) + " not counted");
-    auto *ix = new cobs_index();
-    ix->prm = b->prm;
-    ix->device = b->device;
-    ix->n_docs = b->n_docs;
-    ix->n_terms = b->n_terms;
-    ix->seeds = make_seeds(b->prm.seed);
-    const uint32_t n = b->n_docs, B = b->prm.block_docs;
+    const uint32_t n = ix->n_docs, B = ix->prm.block_docs;
+    ix->seeds = make_seeds(ix->prm.seed);
     ix->order.resize(n);
     std::iota(ix->order.begin(), ix->order.end(), 0u);
     if (B) {
-        // compact: sort by (distinct terms, input id) -- sections 2.2, 2.3
         std::stable_sort(ix->order.begin(), ix->order.end(), [&](uint32_t x, uint32_t y) {
             return ix->n_terms[x] < ix->n_terms[y];
         });
     }
+    ix->blocks.clear();
+    ix->slices.clear();
+    ix->acc_words = 0;
     const uint32_t nb = n == 0 ? 0 : (B ? (n + B - 1) / B : 1);
     uint64_t off = 0;
     for (uint32_t k = 0; k < nb; ++k) {
@@ -405,11 +406,8 @@ cobs_status cobs_builder_plan(cobs_builder *b)
         blk.docs = B ? std::min(B, n - blk.first) : n;
         for (uint32_t j = 0; j < blk.docs; ++j)
             blk.nmax = std::max(blk.nmax, ix->n_terms[ix->order[blk.first + j]]);
-        blk.rows = filter_rows(blk.nmax, b->prm.num_hashes, b->prm.fpr);
-        if (blk.rows > 0xFFFFFFFFull) {
-            delete ix;
-            return set_error(COBS_EINVAL, "block filter exceeds 2^32-1 rows");
-        }
+        blk.rows = filter_rows(blk.nmax, ix->prm.num_hashes, ix->prm.fpr);
+        if (blk.rows > 0xFFFFFFFFull) return set_error(COBS_EINVAL, "block filter exceeds 2^32-1 rows");
         blk.stride = ((blk.docs + 7) / 8 + 127) / 128 * 128;
         blk.offset = off;
         off += blk.rows * blk.stride;
@@ -431,23 +429,52 @@ cobs_status cobs_builder_plan(cobs_builder *b)
             ix->slices.push_back(sd);
         }
     }
-    if (ix->acc_words > 0xFFFFFFFFull) {
-        delete ix;
-        return set_error(COBS_EINVAL, "too many documents for one index");
-    }
+    if (ix->acc_words > 0xFFFFFFFFull) return set_error(COBS_EINVAL, "too many documents for one index");
     ix->total_bytes = off;
+    return COBS_OK;
+}
+
+// Device copies of the order and the slice table.
+cobs_status upload_layout(cobs_index *ix, hipStream_t st)
+{
+    const uint32_t n = ix->n_docs;
+    COBS_HIP(hipMalloc(&ix->d_order, std::max<size_t>(n, 1) * 4));
+    if (n) COBS_HIP(hipMemcpyAsync(ix->d_order, ix->order.data(), n * 4, hipMemcpyHostToDevice, st));
+    COBS_HIP(hipMalloc(&ix->d_slices, std::max<size_t>(ix->slices.size(), 1) * sizeof(SliceDesc)));
+    if (!ix->slices.empty())
+        COBS_HIP(hipMemcpyAsync(ix->d_slices, ix->slices.data(), ix->slices.size() * sizeof(SliceDesc),
+                                hipMemcpyHostToDevice, st));
+    return COBS_OK;
+}
+
+}  // namespace
+
+cobs_status cobs_builder_plan(cobs_builder *b)
+{
+    if (!b) return set_error(COBS_EINVAL, "builder is NULL");
+    if (b->state != 0) return set_error(COBS_ESTATE, "plan called twice");
+    for (uint32_t d = 0; d < b->n_docs; ++d)
+        if (!b->counted[d]) return set_error(COBS_ESTATE, "document " + std::to_string(d) + " not counted");
+    auto *ix = new cobs_index();
+    ix->prm = b->prm;
+    ix->device = b->device;
+    ix->n_docs = b->n_docs;
+    ix->n_terms = b->n_terms;
+    cobs_status s = make_layout(ix);
+    if (s != COBS_OK) {
+        delete ix;
+        return s;
+    }
     b->ix = ix;
+    const uint64_t off = ix->total_bytes;
     if (off) {
         hipError_t e = hipMalloc(&ix->d_matrix, off);
         if (e != hipSuccess) { ix->d_matrix = nullptr; return hip_error(e, "hipMalloc(matrix)"); }
         COBS_HIP(hipMemsetAsync(ix->d_matrix, 0, off, b->st));
     }
-    COBS_HIP(hipMalloc(&ix->d_order, std::max<size_t>(n, 1) * 4));
-    if (n) COBS_HIP(hipMemcpyAsync(ix->d_order, ix->order.data(), n * 4, hipMemcpyHostToDevice, b->st));
-    COBS_HIP(hipMalloc(&ix->d_slices, std::max<size_t>(ix->slices.size(), 1) * sizeof(SliceDesc)));
-    if (!ix->slices.empty())
-        COBS_HIP(hipMemcpyAsync(ix->d_slices, ix->slices.data(), ix->slices.size() * sizeof(SliceDesc),
-                                hipMemcpyHostToDevice, b->st));
+    s = upload_layout(ix, b->st);
+    if (s != COBS_OK) return s;
+    const uint32_t n = b->n_docs;
     b->rank.resize(n);
     for (uint32_t p = 0; p < n; ++p) b->rank[ix->order[p]] = p;
     COBS_HIP(hipStreamSynchronize(b->st));
@@ -571,15 +598,14 @@ cobs_status cobs_index_read(const cobs_index *ix, uint64_t offset, uint64_t nbyt
     return COBS_OK;
 }
 
-cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes)
+namespace {
+
+// Groups of whole consecutive blocks, each within half the device budget.
+cobs_status plan_groups(const cobs_index *ix, uint64_t device_budget_bytes,
+                        std::vector<cobs_index::Group> &groups, uint64_t &stage)
 {
-    if (!ix) return set_error(COBS_EINVAL, "index is NULL");
-    std::lock_guard<std::mutex> g(ix->stream_mu);
-    if (ix->h_matrix) return set_error(COBS_ESTATE, "the matrix is already in host memory");
-    (void)hipSetDevice(ix->device);
     const uint64_t half = device_budget_bytes / 2 & ~uint64_t(255);
-    // groups of whole consecutive blocks, each within one staging buffer
-    std::vector<cobs_index::Group> groups;
+    groups.clear();
     uint32_t s0 = 0;
     for (size_t b = 0; b < ix->blocks.size(); ++b) {
         const Block &blk = ix->blocks[b];
@@ -597,47 +623,234 @@ cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes)
         }
         s0 += ns;
     }
-    uint64_t stage = 0;
+    stage = 0;
     for (const auto &gr : groups) stage = std::max(stage, gr.bytes);
+    return COBS_OK;
+}
+
+// Staging buffers, events, copy stream and rebased slices of a host-resident
+// matrix (ix->h_matrix set); on failure the caller releases the offload state.
+cobs_status setup_staging(cobs_index *ix, const std::vector<cobs_index::Group> &groups, uint64_t stage)
+{
     std::vector<SliceDesc> rebased = ix->slices;
     for (const auto &gr : groups)
         for (uint32_t i = 0; i < gr.n_slices; ++i) rebased[gr.slice0 + i].base -= gr.off;
-    auto fail = [&](cobs_status st) {
-        ix->release_offload();
-        return st;
-    };
+    for (int i = 0; i < 2; ++i) {
+        if (stage) COBS_HIP(hipMalloc(&ix->d_stage[i], stage));
+        COBS_HIP(hipEventCreateWithFlags(&ix->ev_copy[i], hipEventDisableTiming));
+        COBS_HIP(hipEventCreateWithFlags(&ix->ev_done[i], hipEventDisableTiming));
+    }
+    COBS_HIP(hipStreamCreateWithFlags(&ix->copy_stream, hipStreamNonBlocking));
+    COBS_HIP(hipMalloc(&ix->d_group_slices, std::max<size_t>(rebased.size(), 1) * sizeof(SliceDesc)));
+    if (!rebased.empty())
+        COBS_HIP(hipMemcpy(ix->d_group_slices, rebased.data(), rebased.size() * sizeof(SliceDesc),
+                           hipMemcpyHostToDevice));
+    ix->groups = groups;
+    ix->stage_bytes = stage;
+    return COBS_OK;
+}
+
+}  // namespace
+
+cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes)
+{
+    if (!ix) return set_error(COBS_EINVAL, "index is NULL");
+    std::lock_guard<std::mutex> g(ix->stream_mu);
+    if (ix->h_matrix) return set_error(COBS_ESTATE, "the matrix is already in host memory");
+    (void)hipSetDevice(ix->device);
+    std::vector<cobs_index::Group> groups;
+    uint64_t stage = 0;
+    cobs_status s = plan_groups(ix, device_budget_bytes, groups, stage);
+    if (s != COBS_OK) return s;
     hipError_t e = hipHostMalloc((void **)&ix->h_matrix, std::max<uint64_t>(ix->total_bytes, 1));
     if (e != hipSuccess) {
         ix->h_matrix = nullptr;
-        return fail(set_error(COBS_ENOMEM, "pinned host memory for the matrix"));
+        return set_error(COBS_ENOMEM, "pinned host memory for the matrix");
     }
-    if (ix->total_bytes)
-        if ((e = hipMemcpy(ix->h_matrix, ix->d_matrix, ix->total_bytes, hipMemcpyDeviceToHost)) != hipSuccess)
-            return fail(hip_error(e, "hipMemcpy(matrix to host)"));
-    for (int i = 0; i < 2; ++i) {
-        if (stage && (e = hipMalloc(&ix->d_stage[i], stage)) != hipSuccess) {
-            ix->d_stage[i] = nullptr;
-            return fail(hip_error(e, "hipMalloc(staging)"));
-        }
-        if ((e = hipEventCreateWithFlags(&ix->ev_copy[i], hipEventDisableTiming)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&ix->ev_done[i], hipEventDisableTiming)) != hipSuccess)
-            return fail(hip_error(e, "hipEventCreate"));
+    if (ix->total_bytes &&
+        (e = hipMemcpy(ix->h_matrix, ix->d_matrix, ix->total_bytes, hipMemcpyDeviceToHost)) != hipSuccess) {
+        ix->release_offload();
+        return hip_error(e, "hipMemcpy(matrix to host)");
     }
-    if ((e = hipStreamCreateWithFlags(&ix->copy_stream, hipStreamNonBlocking)) != hipSuccess)
-        return fail(hip_error(e, "hipStreamCreate"));
-    if ((e = hipMalloc(&ix->d_group_slices, std::max<size_t>(rebased.size(), 1) * sizeof(SliceDesc))) !=
-        hipSuccess) {
-        ix->d_group_slices = nullptr;
-        return fail(hip_error(e, "hipMalloc(slices)"));
+    if ((s = setup_staging(ix, groups, stage)) != COBS_OK) {
+        ix->release_offload();
+        return s;
     }
-    if (!rebased.empty() &&
-        (e = hipMemcpy(ix->d_group_slices, rebased.data(), rebased.size() * sizeof(SliceDesc),
-                       hipMemcpyHostToDevice)) != hipSuccess)
-        return fail(hip_error(e, "hipMemcpy(slices)"));
-    ix->groups = groups;
-    ix->stage_bytes = stage;
     if (ix->d_matrix) (void)hipFree(ix->d_matrix);
     ix->d_matrix = nullptr;
+    return COBS_OK;
+}
+
+// ---- index files ------------------------------------------------------------------
+
+namespace {
+
+// File layout, little-endian: FileHeader | order u32[n_docs] |
+// n_terms u64[n_docs] | FileBlock[n_blocks] | zero padding to a multiple of
+// 4096 | the matrix (total_bytes: the blocks one after another, each at its
+// offset, as in device memory).  meta_fnv = FNV-1a 64 over the three arrays.
+struct FileHeader {
+    char magic[8];             // "COBSMTX1"
+    uint32_t header_bytes;     // sizeof(FileHeader)
+    uint32_t kind, q, canonical, num_hashes, block_docs;
+    double fpr;
+    uint64_t seed;
+    uint32_t n_docs, n_blocks;
+    uint64_t total_bytes, matrix_offset, meta_fnv;
+};
+
+struct FileBlock {
+    uint32_t first, docs;
+    uint64_t rows, stride, offset;
+};
+
+constexpr char kFileMagic[8] = {'C', 'O', 'B', 'S', 'M', 'T', 'X', '1'};
+constexpr uint64_t kFileChunk = 64ull << 20;
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t n)
+{
+    const uint8_t *b = static_cast<const uint8_t *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001B3ull;
+    return h;
+}
+
+struct File {
+    FILE *f = nullptr;
+    ~File() { if (f) std::fclose(f); }
+};
+
+}  // namespace
+
+cobs_status cobs_index_save(const cobs_index *ix, const char *path)
+{
+    if (!ix || !path) return set_error(COBS_EINVAL, "NULL argument");
+    std::vector<FileBlock> fb;
+    for (const Block &b : ix->blocks) fb.push_back(FileBlock{b.first, b.docs, b.rows, b.stride, b.offset});
+    FileHeader h{};
+    std::memcpy(h.magic, kFileMagic, 8);
+    h.header_bytes = sizeof(FileHeader);
+    h.kind = ix->prm.kind;
+    h.q = ix->prm.q;
+    h.canonical = ix->prm.canonical;
+    h.num_hashes = ix->prm.num_hashes;
+    h.block_docs = ix->prm.block_docs;
+    h.fpr = ix->prm.fpr;
+    h.seed = ix->prm.seed;
+    h.n_docs = ix->n_docs;
+    h.n_blocks = (uint32_t)fb.size();
+    h.total_bytes = ix->total_bytes;
+    const uint64_t meta = sizeof(FileHeader) + (uint64_t)ix->n_docs * 12 + fb.size() * sizeof(FileBlock);
+    h.matrix_offset = (meta + 4095) & ~uint64_t(4095);
+    uint64_t fnv = 0xCBF29CE484222325ull;
+    fnv = fnv1a(fnv, ix->order.data(), ix->order.size() * 4);
+    fnv = fnv1a(fnv, ix->n_terms.data(), ix->n_terms.size() * 8);
+    fnv = fnv1a(fnv, fb.data(), fb.size() * sizeof(FileBlock));
+    h.meta_fnv = fnv;
+    File out;
+    if (!(out.f = std::fopen(path, "wb"))) return set_error(COBS_EINVAL, std::string("cannot create ") + path);
+    std::vector<uint8_t> pad(h.matrix_offset - meta, 0);
+    bool ok = std::fwrite(&h, sizeof h, 1, out.f) == 1 &&
+              std::fwrite(ix->order.data(), 4, ix->n_docs, out.f) == ix->n_docs &&
+              std::fwrite(ix->n_terms.data(), 8, ix->n_docs, out.f) == ix->n_docs &&
+              std::fwrite(fb.data(), sizeof(FileBlock), fb.size(), out.f) == fb.size() &&
+              std::fwrite(pad.data(), 1, pad.size(), out.f) == pad.size();
+    if (ok && ix->h_matrix) {
+        ok = std::fwrite(ix->h_matrix, 1, ix->total_bytes, out.f) == ix->total_bytes;
+    } else if (ok && ix->total_bytes) {
+        (void)hipSetDevice(ix->device);
+        HostBuf stage;
+        COBS_HIP(stage.ensure(std::min(kFileChunk, ix->total_bytes)));
+        for (uint64_t o = 0; ok && o < ix->total_bytes; o += kFileChunk) {
+            const uint64_t nb = std::min(kFileChunk, ix->total_bytes - o);
+            COBS_HIP(hipMemcpy(stage.p, ix->d_matrix + o, nb, hipMemcpyDeviceToHost));
+            ok = std::fwrite(stage.p, 1, nb, out.f) == nb;
+        }
+    }
+    if (!ok || std::fflush(out.f) != 0) return set_error(COBS_EINVAL, std::string("write failed: ") + path);
+    return COBS_OK;
+}
+
+cobs_status cobs_index_load(const char *path, int device, uint64_t device_budget_bytes,
+                            cobs_index **out)
+{
+    if (!path || !out) return set_error(COBS_EINVAL, "NULL argument");
+    *out = nullptr;
+    File in;
+    if (!(in.f = std::fopen(path, "rb"))) return set_error(COBS_EINVAL, std::string("cannot open ") + path);
+    auto bad = [&](const char *why) { return set_error(COBS_EINVAL, std::string(path) + ": " + why); };
+    FileHeader h{};
+    if (std::fread(&h, sizeof h, 1, in.f) != 1) return bad("truncated header");
+    if (std::memcmp(h.magic, kFileMagic, 8) != 0 || h.header_bytes != sizeof(FileHeader))
+        return bad("not an index file of this format");
+    cobs_params prm{};
+    prm.kind = h.kind;
+    prm.q = h.q;
+    prm.canonical = h.canonical;
+    prm.num_hashes = h.num_hashes;
+    prm.fpr = h.fpr;
+    prm.block_docs = h.block_docs;
+    prm.seed = h.seed;
+    cobs_status s = check_params(&prm);
+    if (s != COBS_OK) return s;
+    std::unique_ptr<cobs_index> ix(new cobs_index());
+    ix->prm = prm;
+    ix->device = device;
+    ix->n_docs = h.n_docs;
+    std::vector<uint32_t> order(h.n_docs);
+    ix->n_terms.resize(h.n_docs);
+    std::vector<FileBlock> fb(h.n_blocks);
+    if (std::fread(order.data(), 4, h.n_docs, in.f) != h.n_docs ||
+        std::fread(ix->n_terms.data(), 8, h.n_docs, in.f) != h.n_docs ||
+        std::fread(fb.data(), sizeof(FileBlock), h.n_blocks, in.f) != h.n_blocks)
+        return bad("truncated metadata");
+    uint64_t fnv = 0xCBF29CE484222325ull;
+    fnv = fnv1a(fnv, order.data(), order.size() * 4);
+    fnv = fnv1a(fnv, ix->n_terms.data(), ix->n_terms.size() * 8);
+    fnv = fnv1a(fnv, fb.data(), fb.size() * sizeof(FileBlock));
+    if (fnv != h.meta_fnv) return bad("metadata checksum mismatch");
+    // the layout follows from the counts: recompute it and insist on agreement
+    if ((s = make_layout(ix.get())) != COBS_OK) return s;
+    if (ix->order != order || ix->blocks.size() != fb.size() || ix->total_bytes != h.total_bytes)
+        return bad("layout does not follow from the stored counts");
+    for (size_t b = 0; b < fb.size(); ++b) {
+        const Block &k = ix->blocks[b];
+        if (k.first != fb[b].first || k.docs != fb[b].docs || k.rows != fb[b].rows ||
+            k.stride != fb[b].stride || k.offset != fb[b].offset)
+            return bad("block table does not follow from the stored counts");
+    }
+    if (std::fseek(in.f, (long)h.matrix_offset, SEEK_SET) != 0) return bad("truncated");
+    COBS_HIP(hipSetDevice(device));
+    hipStream_t st = nullptr;
+    if ((s = upload_layout(ix.get(), st)) != COBS_OK) return s;
+    const uint64_t T = ix->total_bytes;
+    if (device_budget_bytes) {
+        std::vector<cobs_index::Group> groups;
+        uint64_t stage = 0;
+        if ((s = plan_groups(ix.get(), device_budget_bytes, groups, stage)) != COBS_OK) return s;
+        if (hipHostMalloc((void **)&ix->h_matrix, std::max<uint64_t>(T, 1)) != hipSuccess) {
+            ix->h_matrix = nullptr;
+            return set_error(COBS_ENOMEM, "pinned host memory for the matrix");
+        }
+        if (T && std::fread(ix->h_matrix, 1, T, in.f) != T) return bad("truncated matrix");
+        if ((s = setup_staging(ix.get(), groups, stage)) != COBS_OK) return s;
+    } else {
+        if (T) {
+            hipError_t e = hipMalloc(&ix->d_matrix, T);
+            if (e != hipSuccess) {
+                ix->d_matrix = nullptr;
+                return set_error(COBS_ENOMEM, "device memory for the matrix");
+            }
+            HostBuf stage;
+            COBS_HIP(stage.ensure(std::min(kFileChunk, T)));
+            for (uint64_t o = 0; o < T; o += kFileChunk) {
+                const uint64_t nb = std::min(kFileChunk, T - o);
+                if (std::fread(stage.p, 1, nb, in.f) != nb) return bad("truncated matrix");
+                COBS_HIP(hipMemcpy(ix->d_matrix + o, stage.p, nb, hipMemcpyHostToDevice));
+            }
+        }
+    }
+    COBS_HIP(hipDeviceSynchronize());
+    *out = ix.release();
     return COBS_OK;
 }
 
