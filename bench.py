@@ -56,9 +56,9 @@ def parse():
     ap.add_argument("--serve-max", type=int, default=8000)
     ap.add_argument("--tuning", type=str, default="",
                     help="'unroll,chunk' launch shape instead of autotuning")
-    ap.add_argument("--offload-gb", type=float, default=0.0,
+    ap.add_argument("--offload-gb", type=float, default=30.0,
                     help="last: move the matrix to host memory and time streamed batches "
-                         "with this device budget (GB) for the staging buffers")
+                         "with this device budget (GB) for the staging buffers; 0 skips it")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -352,14 +352,19 @@ def main():
         log("cpu baseline done")
 
     offload = None
-    if args.offload_gb > 0:
+    if args.offload_gb > 0 and 2 * max(b["rows"] * b["stride"] for b in blocks) <= args.offload_gb * 1e9:
         # out of core: the matrix in pinned host memory, streamed per batch
         t1 = time.time()
-        ix.offload(int(args.offload_gb * 1e9))
+        try:
+            ix.offload(int(args.offload_gb * 1e9))
+        except cobs.CobsError as e:
+            offload = {"error": str(e)}
+    if offload is None and ix.info()["host_resident"]:
         oinfo = ix.info()
         log(f"offloaded in {time.time() - t1:.1f}s: {oinfo['n_groups']} groups, "
             f"staging 2 x {oinfo['stage_bytes'] / 1e9:.2f} GB")
-        ix.query_flat(qdev, q_off, k=k)
+        _, _, oids, oscores = ix.query_flat(qdev, q_off, k=k)
+        same = bool(np.array_equal(oids, ids) and np.array_equal(oscores, sc))
         cobs.profile(True)
         cobs.profile_read(reset=True)
         torch.cuda.synchronize()
@@ -373,7 +378,7 @@ def main():
         ogather = oprof["total_ms"] / max(oprof["launches"], 1)
         offload = {"device_budget_gb": args.offload_gb, "groups": oinfo["n_groups"],
                    "stage_bytes": oinfo["stage_bytes"], "ms_per_step": odt * 1e3,
-                   "lookups_per_s": lookups / odt, "gather_ms": ogather,
+                   "lookups_per_s": lookups / odt, "gather_ms": ogather, "same_hits": same,
                    "host_link_GBps": info["total_bytes"] / (ogather * 1e-3) / 1e9}
         log(f"offloaded: {offload}")
 
