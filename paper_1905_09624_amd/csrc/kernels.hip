@@ -131,18 +131,33 @@ __host__ __device__ __forceinline__ uint64_t table_cap(uint64_t n)
 
 // ---- a1: term extraction ------------------------------------------------------
 
-__global__ void extract_kernel(const uint8_t *bytes, const uint64_t *qstart,
-                               const uint64_t *wbase, uint32_t n, uint64_t W, TermSpec ts,
-                               uint64_t *terms, uint32_t *nterms)
+// Each wavefront takes tiles of 64 x kExtractPerLane consecutive windows
+// (consecutive lanes, consecutive windows: coalesced term writes); the query
+// of a tile's first window is found by one binary search, later windows
+// advance from it.
+constexpr uint32_t kExtractPerLane = 16;
+
+__global__ __launch_bounds__(256) void extract_kernel(const uint8_t *bytes, const uint64_t *qstart,
+                                                      const uint64_t *wbase, uint32_t n, uint64_t W,
+                                                      TermSpec ts, uint64_t *terms, uint32_t *nterms)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         nterms[i] = 0;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < W; w += stride) {
-        const uint32_t qi = bsearch_le(wbase, n, w);
-        bool ok;
-        const uint64_t t = window_term(bytes + qstart[qi] + (w - wbase[qi]), ts, ok);
-        terms[w] = ok ? t : kInvalidTerm;
+    const uint32_t lane = lane_id();
+    const uint64_t tile = 64ull * kExtractPerLane;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t waves = stride >> 6;
+    for (uint64_t t0 = wave * tile; t0 < W; t0 += waves * tile) {
+        uint32_t qi = bsearch_le(wbase, n, t0);
+        for (uint32_t i = 0; i < kExtractPerLane; ++i) {
+            const uint64_t w = t0 + (uint64_t)i * 64 + lane;
+            if (w >= W) break;
+            while (w >= wbase[qi + 1]) ++qi;
+            bool ok;
+            const uint64_t t = window_term(bytes + qstart[qi] + (w - wbase[qi]), ts, ok);
+            terms[w] = ok ? t : kInvalidTerm;
+        }
     }
 }
 
@@ -751,11 +766,14 @@ __global__ __launch_bounds__(1024) void segsort_kernel(uint64_t *seg_a, uint64_t
     uint64_t *src = seg_a + beg, *dst = seg_b + beg;
     for (uint32_t r0 = 0; r0 < n; r0 += kSortRun) {
         const uint32_t rn = min(kSortRun, n - r0);
-        for (uint32_t i = tid; i < kSortRun; i += nt) s[i] = i < rn ? src[r0 + i] : 0ull;
+        if (rn < 2) break;   // a run of one is sorted (only the last run can be short)
+        uint32_t m = 2;      // bitonic network over the next power of two
+        while (m < rn) m <<= 1;
+        for (uint32_t i = tid; i < m; i += nt) s[i] = i < rn ? src[r0 + i] : 0ull;
         __syncthreads();
-        for (uint32_t k = 2; k <= kSortRun; k <<= 1) {
+        for (uint32_t k = 2; k <= m; k <<= 1) {
             for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = tid; i < kSortRun; i += nt) {
+                for (uint32_t i = tid; i < m; i += nt) {
                     const uint32_t ixj = i ^ j;
                     if (ixj > i) {
                         const uint64_t x = s[i], y = s[ixj];
@@ -919,8 +937,10 @@ hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const ui
                           uint32_t *nterms, hipStream_t st)
 {
     if (n_queries == 0) return hipSuccess;
-    hipLaunchKernelGGL(extract_kernel, dim3(grid_for(std::max<uint64_t>(W, n_queries), 256)),
-                       dim3(256), 0, st, bytes, qstart, wbase, n_queries, W, ts, terms, nterms);
+    const uint64_t tiles = (W + 64ull * kExtractPerLane - 1) / (64ull * kExtractPerLane);
+    hipLaunchKernelGGL(extract_kernel,
+                       dim3(grid_for(std::max<uint64_t>(tiles * 64, n_queries), 256)), dim3(256), 0,
+                       st, bytes, qstart, wbase, n_queries, W, ts, terms, nterms);
     return hipGetLastError();
 }
 
