@@ -94,6 +94,7 @@ struct GatherArgs {
 
 // a1: one term per window of every query (kInvalidTerm for DNA windows with
 // a non-ACGT byte).  qstart[i]: first byte of query i; wbase[i]: first window.
+// bytes: 4-byte aligned, with 64 readable bytes after the last query.
 // Also zeroes nterms[0, n_queries).
 hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const uint64_t *wbase,
                           uint32_t n_queries, uint64_t total_windows, TermSpec ts,

@@ -55,6 +55,47 @@ __device__ __forceinline__ uint64_t window_term(const uint8_t *s, const TermSpec
     return t;
 }
 
+// The same from aligned dword loads: the 36 bytes from the dword holding
+// s[0] (s must have at least 35 readable bytes after it), realigned with
+// v_alignbyte; nine loads per window instead of q byte loads.
+__device__ __forceinline__ uint64_t window_term_dw(const uint8_t *s, const TermSpec ts, bool &ok)
+{
+    const uint32_t o = (uint32_t)((uintptr_t)s & 3u);
+    const uint32_t *wp = (const uint32_t *)(s - o);
+    uint32_t w[9];
+    if (ts.kind == 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[k] = wp[k];
+        const uint64_t lo = __builtin_amdgcn_alignbyte(w[1], w[0], o);
+        const uint64_t hi = __builtin_amdgcn_alignbyte(w[2], w[1], o);
+        const uint64_t t = lo | (hi << 32);
+        ok = true;
+        return ts.q >= 8 ? t : t & ((1ull << (8 * ts.q)) - 1);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = wp[k];
+    uint64_t t = 0, rc = 0;
+    bool valid = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t a = __builtin_amdgcn_alignbyte(w[k + 1], w[k], o);   // bytes 4k .. 4k+3
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t j = 4 * k + b;
+            if (j < ts.q) {
+                const uint32_t u = (a >> (8 * b)) & 0xDFu;
+                valid &= (u == 'A') | (u == 'C') | (u == 'G') | (u == 'T');
+                const uint32_t c = ((u >> 1) ^ (u >> 2)) & 3u;
+                t = (t << 2) | c;
+                rc |= (uint64_t)(3u - c) << (2 * j);
+            }
+        }
+    }
+    ok = valid;
+    if (ts.canonical && rc < t) t = rc;
+    return t;
+}
+
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -155,7 +196,7 @@ __global__ __launch_bounds__(256) void extract_kernel(const uint8_t *bytes, cons
             if (w >= W) break;
             while (w >= wbase[qi + 1]) ++qi;
             bool ok;
-            const uint64_t t = window_term(bytes + qstart[qi] + (w - wbase[qi]), ts, ok);
+            const uint64_t t = window_term_dw(bytes + qstart[qi] + (w - wbase[qi]), ts, ok);
             terms[w] = ok ? t : kInvalidTerm;
         }
     }

@@ -988,7 +988,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         return set_error(COBS_EINVAL, "mem must be COBS_MEM_HOST or COBS_MEM_DEVICE");
     const uint32_t q = ix->prm.q, h = ix->prm.num_hashes;
     const uint32_t n_slices = (uint32_t)ix->slices.size();
-    const uint64_t byte0 = b.mem == COBS_MEM_HOST ? b.q_off[0] : 0;
+    const uint64_t byte0 = b.q_off[0];
     const uint64_t nbytes = b.q_off[n] - b.q_off[0];
     if (nbytes && !b.bytes) return set_error(COBS_EINVAL, "bytes is NULL");
 
@@ -1054,15 +1054,16 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     const uint64_t *d_tbase = (const uint64_t *)(ws.meta.as<uint8_t>() + o_tb);
     const uint32_t *d_bprefix = (const uint32_t *)(ws.meta.as<uint8_t>() + o_bp);
     const uint32_t *d_slot = b.slots ? (const uint32_t *)(ws.meta.as<uint8_t>() + o_sl) : nullptr;
-    const uint8_t *dbytes = b.bytes;
-    if (b.mem == COBS_MEM_HOST) {
-        COBS_HIP(ws.bytes.ensure(nbytes + 64));
-        if (nbytes) {
-            std::memcpy(stg + meta, b.bytes + byte0, nbytes);
-            COBS_HIP(hipMemcpyAsync(ws.bytes.p, stg + meta, nbytes, hipMemcpyHostToDevice, st));
-        }
-        dbytes = ws.bytes.as<uint8_t>();
+    // the query bytes in the workspace (256-byte aligned, 64 bytes of slack:
+    // the extract kernel reads whole aligned dwords around each window)
+    COBS_HIP(ws.bytes.ensure(nbytes + 64));
+    if (nbytes && b.mem == COBS_MEM_HOST) {
+        std::memcpy(stg + meta, b.bytes + byte0, nbytes);
+        COBS_HIP(hipMemcpyAsync(ws.bytes.p, stg + meta, nbytes, hipMemcpyHostToDevice, st));
+    } else if (nbytes) {
+        COBS_HIP(hipMemcpyAsync(ws.bytes.p, b.bytes + byte0, nbytes, hipMemcpyDeviceToDevice, st));
     }
+    const uint8_t *dbytes = ws.bytes.as<uint8_t>();
 
     // a1-a3
     COBS_HIP(ws.terms.ensure(std::max<uint64_t>(W, 1) * 8));
