@@ -257,32 +257,43 @@ __device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint6
     }
 }
 
-// One workgroup per query whose set fits in LDS; queries with a global table
-// (cleared to kEmpty beforehand, cap slots plus one flag word) are spread over
-// several workgroups, which count into nterms (zeroed by the extract kernel).
-// bprefix[i]: first workgroup of query i.
-__global__ __launch_bounds__(256) void dedup_kernel(const uint64_t *terms, const uint64_t *wbase,
-                                                    const uint64_t *tbase, const uint32_t *bprefix,
-                                                    uint32_t n, uint64_t *gtable, uint64_t *uterms,
-                                                    uint64_t *hashes, uint32_t *nterms, TermSpec ts,
-                                                    Seeds seeds)
+// One workgroup per query whose set fits in LDS (lds_q: those queries).
+__global__ __launch_bounds__(256) void dedup_lds_kernel(const uint64_t *terms, const uint64_t *wbase,
+                                                        const uint32_t *lds_q, uint64_t *uterms,
+                                                        uint64_t *hashes, uint32_t *nterms,
+                                                        TermSpec ts, Seeds seeds)
 {
     __shared__ uint64_t ltable[kLdsTableSlots];
     __shared__ uint64_t lflag;
     __shared__ uint32_t lcount;
-    const uint32_t qi = bsearch_le(bprefix, n, blockIdx.x);
-    const uint32_t part = blockIdx.x - bprefix[qi];
+    const uint32_t qi = lds_q[blockIdx.x];
     const uint64_t w0 = wbase[qi], nw = wbase[qi + 1] - w0;
     const uint64_t cap = table_cap(nw);
-    if (cap <= kLdsTableSlots) {
-        if (threadIdx.x == 0) { lcount = 0; lflag = kEmpty; }
-        for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) ltable[s] = kEmpty;
-        __syncthreads();
-        dedup_range(ltable, cap, &lflag, terms, w0, 0, nw, uterms, hashes, ts, seeds, &lcount);
-        __syncthreads();
-        if (threadIdx.x == 0) nterms[qi] = lcount;
-        return;
-    }
+    if (threadIdx.x == 0) { lcount = 0; lflag = kEmpty; }
+    for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) ltable[s] = kEmpty;
+    __syncthreads();
+    dedup_range(ltable, cap, &lflag, terms, w0, 0, nw, uterms, hashes, ts, seeds, &lcount);
+    __syncthreads();
+    if (threadIdx.x == 0) nterms[qi] = lcount;
+}
+
+// Queries with a global table (cleared to kEmpty beforehand: cap slots plus
+// one flag word at tbase[i]), kDedupWindowsPerGroup windows per workgroup,
+// counting into nterms (zeroed by the extract kernel).  No LDS, so many
+// workgroups per CU hide the latency of the table's atomics.  g_q: those
+// queries; gprefix[j]: first workgroup of g_q[j].
+__global__ __launch_bounds__(256) void dedup_global_kernel(const uint64_t *terms, const uint64_t *wbase,
+                                                           const uint64_t *tbase, const uint32_t *g_q,
+                                                           const uint32_t *gprefix, uint32_t n_g,
+                                                           uint64_t *gtable, uint64_t *uterms,
+                                                           uint64_t *hashes, uint32_t *nterms,
+                                                           TermSpec ts, Seeds seeds)
+{
+    const uint32_t j = bsearch_le(gprefix, n_g, blockIdx.x);
+    const uint32_t qi = g_q[j];
+    const uint32_t part = blockIdx.x - gprefix[j];
+    const uint64_t w0 = wbase[qi], nw = wbase[qi + 1] - w0;
+    const uint64_t cap = table_cap(nw);
     uint64_t *table = gtable + tbase[qi];
     const uint64_t b = (uint64_t)part * kDedupWindowsPerGroup;
     const uint64_t e = min(nw, b + kDedupWindowsPerGroup);
@@ -986,18 +997,20 @@ hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const ui
 }
 
 hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint64_t *tbase,
-                        const uint32_t *bprefix, uint32_t n_groups, uint64_t *table,
+                        const uint32_t *lds_q, uint32_t n_lds, const uint32_t *g_q,
+                        const uint32_t *gprefix, uint32_t n_g, uint32_t g_groups, uint64_t *table,
                         uint64_t table_slots, uint64_t *uterms, uint64_t *hashes,
-                        uint32_t *nterms, uint32_t n_queries, TermSpec ts, Seeds seeds,
-                        hipStream_t st)
+                        uint32_t *nterms, TermSpec ts, Seeds seeds, hipStream_t st)
 {
-    if (n_queries == 0) return hipSuccess;
-    if (table_slots) {
+    if (n_lds)
+        hipLaunchKernelGGL(dedup_lds_kernel, dim3(n_lds), dim3(256), 0, st, terms, wbase, lds_q,
+                           uterms, hashes, nterms, ts, seeds);
+    if (n_g) {
         hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(table_slots, 256)), dim3(256), 0, st,
                            table, table_slots, kEmpty);
+        hipLaunchKernelGGL(dedup_global_kernel, dim3(g_groups), dim3(256), 0, st, terms, wbase,
+                           tbase, g_q, gprefix, n_g, table, uterms, hashes, nterms, ts, seeds);
     }
-    hipLaunchKernelGGL(dedup_kernel, dim3(n_groups), dim3(256), 0, st, terms, wbase, tbase,
-                       bprefix, n_queries, table, uterms, hashes, nterms, ts, seeds);
     return hipGetLastError();
 }
 

@@ -905,10 +905,11 @@ struct Scalars {
     uint32_t pad;
 };
 
+// qstart, wbase, tbase (u64); slot, lds_q + g_q (n entries together), gprefix (u32)
 size_t batch_meta_bytes(uint32_t n)
 {
-    return ((size_t)n * 8 + (size_t)(n + 1) * 8 + (size_t)n * 8 + (size_t)(n + 1) * 4 +
-            (size_t)n * 4 + 15) & ~size_t(15);
+    return ((size_t)n * 8 + (size_t)(n + 1) * 8 + (size_t)n * 8 + (size_t)n * 4 + (size_t)n * 4 +
+            (size_t)(n + 1) * 4 + 15) & ~size_t(15);
 }
 
 // Terms per work item: enough items to keep every resident wavefront busy
@@ -1006,18 +1007,26 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         maxw = std::max(maxw, nw);
     }
     wbase[n] = W;
+    // dedup work lists: queries with an LDS set; queries with a global table
+    // and the first workgroup of each
     std::vector<uint64_t> tb(n, 0);
-    std::vector<uint32_t> bprefix(n + 1, 0);
+    std::vector<uint32_t> lds_q, g_q, gprefix;
     uint64_t groups = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t nw = wbase[i + 1] - wbase[i];
+        const uint64_t slots = dedup_table_slots(nw);
         tb[i] = tslots;
-        tslots += dedup_table_slots(nw);
-        bprefix[i] = (uint32_t)groups;
-        groups += dedup_groups(nw);
+        tslots += slots;
+        if (slots) {
+            g_q.push_back(i);
+            gprefix.push_back((uint32_t)groups);
+            groups += dedup_groups(nw);
+        } else {
+            lds_q.push_back(i);
+        }
     }
     if (groups > 0x7FFFFFFFull) return set_error(COBS_EINVAL, "query batch too large");
-    bprefix[n] = (uint32_t)groups;
+    gprefix.push_back((uint32_t)groups);
     const int planes = gather_planes_for(maxw);
     int unroll = b.unroll ? (int)b.unroll : (ix->tuned_unroll ? ix->tuned_unroll : gather_default_unroll((int)h));
     if (!gather_unroll_valid(unroll, (int)h)) unroll = gather_default_unroll((int)h);
@@ -1036,24 +1045,29 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     const TermSpec ts = term_spec(ix->prm);
 
     // uploads
-    // staging: qstart | wbase | tbase | bprefix | slot | query bytes (host mode)
-    const size_t o_wb = (size_t)n * 8, o_tb = o_wb + (size_t)(n + 1) * 8, o_bp = o_tb + (size_t)n * 8;
-    const size_t o_sl = o_bp + (size_t)(n + 1) * 4;
+    // staging: qstart | wbase | tbase | slot | lds_q | g_q | gprefix | query bytes (host mode)
+    const size_t o_wb = (size_t)n * 8, o_tb = o_wb + (size_t)(n + 1) * 8, o_sl = o_tb + (size_t)n * 8;
+    const size_t o_lq = o_sl + (size_t)n * 4, o_gq = o_lq + lds_q.size() * 4;
+    const size_t o_gp = o_gq + g_q.size() * 4;
     const size_t meta = batch_meta_bytes(n);
     COBS_HIP(ws.h_stage.ensure(meta + (b.mem == COBS_MEM_HOST ? nbytes : 0)));
     uint8_t *stg = ws.h_stage.as<uint8_t>();
     std::memcpy(stg, qstart, (size_t)n * 8);
     std::memcpy(stg + o_wb, wbase, (size_t)(n + 1) * 8);
     std::memcpy(stg + o_tb, tb.data(), (size_t)n * 8);
-    std::memcpy(stg + o_bp, bprefix.data(), (size_t)(n + 1) * 4);
     if (b.slots) std::memcpy(stg + o_sl, b.slots, (size_t)n * 4);
+    std::memcpy(stg + o_lq, lds_q.data(), lds_q.size() * 4);
+    std::memcpy(stg + o_gq, g_q.data(), g_q.size() * 4);
+    std::memcpy(stg + o_gp, gprefix.data(), gprefix.size() * 4);
     COBS_HIP(ws.meta.ensure(meta));
     COBS_HIP(hipMemcpyAsync(ws.meta.p, stg, meta, hipMemcpyHostToDevice, st));
     const uint64_t *d_qstart = ws.meta.as<uint64_t>();
     const uint64_t *d_wbase = (const uint64_t *)(ws.meta.as<uint8_t>() + o_wb);
     const uint64_t *d_tbase = (const uint64_t *)(ws.meta.as<uint8_t>() + o_tb);
-    const uint32_t *d_bprefix = (const uint32_t *)(ws.meta.as<uint8_t>() + o_bp);
     const uint32_t *d_slot = b.slots ? (const uint32_t *)(ws.meta.as<uint8_t>() + o_sl) : nullptr;
+    const uint32_t *d_lds_q = (const uint32_t *)(ws.meta.as<uint8_t>() + o_lq);
+    const uint32_t *d_g_q = (const uint32_t *)(ws.meta.as<uint8_t>() + o_gq);
+    const uint32_t *d_gprefix = (const uint32_t *)(ws.meta.as<uint8_t>() + o_gp);
     // the query bytes in the workspace (256-byte aligned, 64 bytes of slack:
     // the extract kernel reads whole aligned dwords around each window)
     COBS_HIP(ws.bytes.ensure(nbytes + 64));
@@ -1073,9 +1087,10 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     COBS_HIP(ws.table.ensure(std::max<uint64_t>(tslots, 1) * 8));
     COBS_HIP(launch_extract(dbytes, d_qstart, d_wbase, n, W, ts, ws.terms.as<uint64_t>(),
                             ws.nterms.as<uint32_t>(), st));
-    COBS_HIP(launch_dedup(ws.terms.as<uint64_t>(), d_wbase, d_tbase, d_bprefix, (uint32_t)groups,
+    COBS_HIP(launch_dedup(ws.terms.as<uint64_t>(), d_wbase, d_tbase, d_lds_q, (uint32_t)lds_q.size(),
+                          d_g_q, d_gprefix, (uint32_t)g_q.size(), (uint32_t)groups,
                           ws.table.as<uint64_t>(), tslots, ws.uterms.as<uint64_t>(),
-                          ws.hashes.as<uint64_t>(), ws.nterms.as<uint32_t>(), n, ts, ix->seeds, st));
+                          ws.hashes.as<uint64_t>(), ws.nterms.as<uint32_t>(), ts, ix->seeds, st));
     if (b.terms_out) {
         std::vector<uint32_t> nt(n);
         COBS_HIP(hipMemcpyAsync(nt.data(), ws.nterms.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
