@@ -13,7 +13,7 @@ constexpr uint32_t kSliceBytes = 1024;     // one wavefront: 64 lanes x 16 bytes
 constexpr uint32_t kLdsTableSlots = 8192;  // dedup table held in LDS (64 KiB)
 constexpr uint32_t kSortRun = 2048;        // candidates sorted in LDS per run
 constexpr uint32_t kSliceDocs = 8192;      // documents per slice (score buffer stride)
-constexpr uint32_t kDedupWindowsPerGroup = 2048;  // windows per workgroup of a global-table query
+constexpr uint32_t kDedupWindowsPerGroup = 16384; // windows per workgroup of a global-table query
 constexpr uint32_t kDefaultChunkCap = 16384;      // largest automatic work item (terms)
 
 struct Seeds {

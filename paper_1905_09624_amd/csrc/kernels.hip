@@ -204,15 +204,25 @@ __global__ __launch_bounds__(256) void extract_kernel(const uint8_t *bytes, cons
 
 // ---- a2 + a3: per-query term set and hashes ----------------------------------------
 
+// 64-bit compare-and-swap at the given memory scope; returns the old value.
+template <int kScope>
+__device__ __forceinline__ uint64_t cas64(uint64_t *p, uint64_t expected, uint64_t desired)
+{
+    unsigned long long e = expected;
+    __hip_atomic_compare_exchange_strong((unsigned long long *)p, &e, (unsigned long long)desired,
+                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED, kScope);
+    return e;
+}
+
 // Insert t (!= kEmpty, which marks free slots) into an open-addressing set,
 // linear probing from slot; true when t was not there yet.  Callers record the
-// term kEmpty itself in a flag word.
+// term kEmpty itself in a flag word.  kScope: the widest scope of the threads
+// sharing the table (one workgroup, or several on any CU).
+template <int kScope>
 __device__ __forceinline__ bool set_insert(uint64_t *table, uint64_t cap, uint64_t t, uint64_t slot)
 {
     for (;;) {
-        const unsigned long long old =
-            atomicCAS((unsigned long long *)&table[slot], (unsigned long long)kEmpty,
-                      (unsigned long long)t);
+        const uint64_t old = cas64<kScope>(&table[slot], kEmpty, t);
         if (old == kEmpty) return true;
         if (old == t) return false;
         slot = (slot + 1) & (cap - 1);
@@ -221,6 +231,7 @@ __device__ __forceinline__ bool set_insert(uint64_t *table, uint64_t cap, uint64
 
 // Windows [b, e) of one query: insert every valid term; each wavefront
 // reserves output positions for its new terms with one atomic add on count.
+template <int kScope>
 __device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint64_t *flag,
                                             const uint64_t *terms, uint64_t w0, uint64_t b,
                                             uint64_t e, uint64_t *uterms, uint64_t *hashes,
@@ -237,15 +248,15 @@ __device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint6
 #pragma unroll
                 for (int i = 0; i < kMaxHashes; ++i)
                     if (i < (int)ts.h) hs[i] = mix64(t ^ seeds.s[i]);
-                fresh = t == kEmpty ? atomicCAS((unsigned long long *)flag,
-                                                (unsigned long long)kEmpty, 0ull) == kEmpty
-                                    : set_insert(table, cap, t, hs[0] & (cap - 1));
+                fresh = t == kEmpty ? cas64<kScope>(flag, kEmpty, 0) == kEmpty
+                                    : set_insert<kScope>(table, cap, t, hs[0] & (cap - 1));
             }
         }
         const uint64_t m = __ballot(fresh);
         if (m == 0) continue;
         uint32_t pos0 = 0;
-        if (lane == (uint32_t)__builtin_ctzll(m)) pos0 = atomicAdd(count, (uint32_t)__popcll(m));
+        if (lane == (uint32_t)__builtin_ctzll(m))
+            pos0 = __hip_atomic_fetch_add(count, (uint32_t)__popcll(m), __ATOMIC_RELAXED, kScope);
         pos0 = lane_u32(pos0, (uint32_t)__builtin_ctzll(m));
         if (fresh) {
             const uint64_t pos = w0 + pos0 + __popcll(m & ((1ull << lane) - 1ull));
@@ -272,32 +283,46 @@ __global__ __launch_bounds__(256) void dedup_lds_kernel(const uint64_t *terms, c
     if (threadIdx.x == 0) { lcount = 0; lflag = kEmpty; }
     for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) ltable[s] = kEmpty;
     __syncthreads();
-    dedup_range(ltable, cap, &lflag, terms, w0, 0, nw, uterms, hashes, ts, seeds, &lcount);
+    dedup_range<__HIP_MEMORY_SCOPE_WORKGROUP>(ltable, cap, &lflag, terms, w0, 0, nw, uterms, hashes,
+                                              ts, seeds, &lcount);
     __syncthreads();
     if (threadIdx.x == 0) nterms[qi] = lcount;
 }
 
 // Queries with a global table (cleared to kEmpty beforehand: cap slots plus
-// one flag word at tbase[i]), kDedupWindowsPerGroup windows per workgroup,
-// counting into nterms (zeroed by the extract kernel).  No LDS, so many
-// workgroups per CU hide the latency of the table's atomics.  g_q: those
-// queries; gprefix[j]: first workgroup of g_q[j].
-__global__ __launch_bounds__(256) void dedup_global_kernel(const uint64_t *terms, const uint64_t *wbase,
-                                                           const uint64_t *tbase, const uint32_t *g_q,
-                                                           const uint32_t *gprefix, uint32_t n_g,
-                                                           uint64_t *gtable, uint64_t *uterms,
-                                                           uint64_t *hashes, uint32_t *nterms,
-                                                           TermSpec ts, Seeds seeds)
+// one flag word at tbase[i]), kDedupWindowsPerGroup windows per workgroup of
+// 1024 threads.  A query of one workgroup keeps its atomics at workgroup
+// scope (served by its XCD's L2) and counts in LDS; a longer one spreads over
+// several workgroups with device-scope atomics, counting into nterms (zeroed
+// by the extract kernel).  g_q: those queries; gprefix[j]: first workgroup of
+// g_q[j].
+__global__ __launch_bounds__(1024) void dedup_global_kernel(const uint64_t *terms, const uint64_t *wbase,
+                                                            const uint64_t *tbase, const uint32_t *g_q,
+                                                            const uint32_t *gprefix, uint32_t n_g,
+                                                            uint64_t *gtable, uint64_t *uterms,
+                                                            uint64_t *hashes, uint32_t *nterms,
+                                                            TermSpec ts, Seeds seeds)
 {
+    __shared__ uint32_t lcount;
     const uint32_t j = bsearch_le(gprefix, n_g, blockIdx.x);
     const uint32_t qi = g_q[j];
     const uint32_t part = blockIdx.x - gprefix[j];
     const uint64_t w0 = wbase[qi], nw = wbase[qi + 1] - w0;
     const uint64_t cap = table_cap(nw);
     uint64_t *table = gtable + tbase[qi];
+    if (nw <= kDedupWindowsPerGroup) {
+        if (threadIdx.x == 0) lcount = 0;
+        __syncthreads();
+        dedup_range<__HIP_MEMORY_SCOPE_WORKGROUP>(table, cap, table + cap, terms, w0, 0, nw, uterms,
+                                                  hashes, ts, seeds, &lcount);
+        __syncthreads();
+        if (threadIdx.x == 0) nterms[qi] = lcount;
+        return;
+    }
     const uint64_t b = (uint64_t)part * kDedupWindowsPerGroup;
     const uint64_t e = min(nw, b + kDedupWindowsPerGroup);
-    dedup_range(table, cap, table + cap, terms, w0, b, e, uterms, hashes, ts, seeds, &nterms[qi]);
+    dedup_range<__HIP_MEMORY_SCOPE_AGENT>(table, cap, table + cap, terms, w0, b, e, uterms, hashes, ts,
+                                          seeds, &nterms[qi]);
 }
 
 // ---- plan ------------------------------------------------------------------------------
@@ -889,7 +914,8 @@ __global__ __launch_bounds__(256) void count_kernel(const uint8_t *bytes, const 
             if (ok) {
                 const uint64_t cap = 1ull << tlog2[d];
                 uniq = t == kEmpty ? atomicOr(&empty_flag[d], 1u) == 0
-                                   : set_insert(table + tbase[d], cap, t, mix64(t) & (cap - 1));
+                                   : set_insert<__HIP_MEMORY_SCOPE_AGENT>(table + tbase[d], cap, t,
+                                                                          mix64(t) & (cap - 1));
             }
         }
         const uint32_t d0 = uniform_u32(d);
@@ -1008,7 +1034,7 @@ hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint
     if (n_g) {
         hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(table_slots, 256)), dim3(256), 0, st,
                            table, table_slots, kEmpty);
-        hipLaunchKernelGGL(dedup_global_kernel, dim3(g_groups), dim3(256), 0, st, terms, wbase,
+        hipLaunchKernelGGL(dedup_global_kernel, dim3(g_groups), dim3(1024), 0, st, terms, wbase,
                            tbase, g_q, gprefix, n_g, table, uterms, hashes, nterms, ts, seeds);
     }
     return hipGetLastError();
