@@ -268,13 +268,16 @@ __device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint6
     }
 }
 
-// One workgroup per query whose set fits in LDS (lds_q: those queries).
-__global__ __launch_bounds__(256) void dedup_lds_kernel(const uint64_t *terms, const uint64_t *wbase,
-                                                        const uint32_t *lds_q, uint64_t *uterms,
-                                                        uint64_t *hashes, uint32_t *nterms,
-                                                        TermSpec ts, Seeds seeds)
+// One workgroup per query whose set fits in kSlots LDS slots (lds_q: those
+// queries): 64 KiB tables for up to 4,096 windows, 128 KiB tables (one
+// workgroup of 1,024 threads per CU) for up to 8,192.
+template <uint32_t kSlots, int kThreads>
+__global__ __launch_bounds__(kThreads) void dedup_lds_kernel(const uint64_t *terms, const uint64_t *wbase,
+                                                             const uint32_t *lds_q, uint64_t *uterms,
+                                                             uint64_t *hashes, uint32_t *nterms,
+                                                             TermSpec ts, Seeds seeds)
 {
-    __shared__ uint64_t ltable[kLdsTableSlots];
+    __shared__ uint64_t ltable[kSlots];
     __shared__ uint64_t lflag;
     __shared__ uint32_t lcount;
     const uint32_t qi = lds_q[blockIdx.x];
@@ -1023,14 +1026,18 @@ hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const ui
 }
 
 hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint64_t *tbase,
-                        const uint32_t *lds_q, uint32_t n_lds, const uint32_t *g_q,
-                        const uint32_t *gprefix, uint32_t n_g, uint32_t g_groups, uint64_t *table,
-                        uint64_t table_slots, uint64_t *uterms, uint64_t *hashes,
-                        uint32_t *nterms, TermSpec ts, Seeds seeds, hipStream_t st)
+                        const uint32_t *lds_q, uint32_t n_small, uint32_t n_large,
+                        const uint32_t *g_q, const uint32_t *gprefix, uint32_t n_g,
+                        uint32_t g_groups, uint64_t *table, uint64_t table_slots,
+                        uint64_t *uterms, uint64_t *hashes, uint32_t *nterms, TermSpec ts,
+                        Seeds seeds, hipStream_t st)
 {
-    if (n_lds)
-        hipLaunchKernelGGL(dedup_lds_kernel, dim3(n_lds), dim3(256), 0, st, terms, wbase, lds_q,
-                           uterms, hashes, nterms, ts, seeds);
+    if (n_small)
+        hipLaunchKernelGGL((dedup_lds_kernel<kLdsTableSlots / 2, 256>), dim3(n_small), dim3(256), 0, st,
+                           terms, wbase, lds_q, uterms, hashes, nterms, ts, seeds);
+    if (n_large)
+        hipLaunchKernelGGL((dedup_lds_kernel<kLdsTableSlots, 1024>), dim3(n_large), dim3(1024), 0, st,
+                           terms, wbase, lds_q + n_small, uterms, hashes, nterms, ts, seeds);
     if (n_g) {
         hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(table_slots, 256)), dim3(256), 0, st,
                            table, table_slots, kEmpty);
@@ -1045,6 +1052,8 @@ uint64_t dedup_table_slots(uint64_t windows)
     const uint64_t cap = table_cap(windows);
     return cap <= kLdsTableSlots ? 0 : cap + 1;
 }
+
+bool dedup_small_table(uint64_t windows) { return table_cap(windows) <= kLdsTableSlots / 2; }
 
 uint32_t dedup_groups(uint64_t windows)
 {

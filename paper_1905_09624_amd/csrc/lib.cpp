@@ -1010,7 +1010,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     // dedup work lists: queries with an LDS set; queries with a global table
     // and the first workgroup of each
     std::vector<uint64_t> tb(n, 0);
-    std::vector<uint32_t> lds_q, g_q, gprefix;
+    std::vector<uint32_t> lds_q, lds_large, g_q, gprefix;
     uint64_t groups = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t nw = wbase[i + 1] - wbase[i];
@@ -1021,10 +1021,14 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
             g_q.push_back(i);
             gprefix.push_back((uint32_t)groups);
             groups += dedup_groups(nw);
-        } else {
+        } else if (dedup_small_table(nw)) {
             lds_q.push_back(i);
+        } else {
+            lds_large.push_back(i);
         }
     }
+    const uint32_t n_small = (uint32_t)lds_q.size();
+    lds_q.insert(lds_q.end(), lds_large.begin(), lds_large.end());
     if (groups > 0x7FFFFFFFull) return set_error(COBS_EINVAL, "query batch too large");
     gprefix.push_back((uint32_t)groups);
     const int planes = gather_planes_for(maxw);
@@ -1087,10 +1091,11 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     COBS_HIP(ws.table.ensure(std::max<uint64_t>(tslots, 1) * 8));
     COBS_HIP(launch_extract(dbytes, d_qstart, d_wbase, n, W, ts, ws.terms.as<uint64_t>(),
                             ws.nterms.as<uint32_t>(), st));
-    COBS_HIP(launch_dedup(ws.terms.as<uint64_t>(), d_wbase, d_tbase, d_lds_q, (uint32_t)lds_q.size(),
-                          d_g_q, d_gprefix, (uint32_t)g_q.size(), (uint32_t)groups,
-                          ws.table.as<uint64_t>(), tslots, ws.uterms.as<uint64_t>(),
-                          ws.hashes.as<uint64_t>(), ws.nterms.as<uint32_t>(), ts, ix->seeds, st));
+    COBS_HIP(launch_dedup(ws.terms.as<uint64_t>(), d_wbase, d_tbase, d_lds_q, n_small,
+                          (uint32_t)lds_large.size(), d_g_q, d_gprefix, (uint32_t)g_q.size(),
+                          (uint32_t)groups, ws.table.as<uint64_t>(), tslots,
+                          ws.uterms.as<uint64_t>(), ws.hashes.as<uint64_t>(),
+                          ws.nterms.as<uint32_t>(), ts, ix->seeds, st));
     if (b.terms_out) {
         std::vector<uint32_t> nt(n);
         COBS_HIP(hipMemcpyAsync(nt.data(), ws.nterms.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));

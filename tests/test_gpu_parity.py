@@ -236,13 +236,15 @@ def test_edge_queries():
 
 
 def test_long_query_multi_chunk_and_global_table():
-    # > 4096 windows: dedup table in global memory; > 1024 terms: several
+    # > 8192 windows: dedup table in global memory (> 16384: several
+    # workgroups); 5,000-8,192 windows: the 128 KiB LDS table; > 1024 terms: several
     # chunks merged by the last wavefront of each (query, slice)
     rng = np.random.default_rng(6)
     docs = oracle.Docs.from_lists([rand_dna(rng, 30000) for _ in range(12)])
     gix, oix = build_both(docs, 0, 31, True, 1, 0.3, 4, 2)
     d0 = docs.bytes[int(docs.str_off[0]):int(docs.str_off[1])].tobytes()
-    qs = [d0[:20000] + rand_dna(rng, 30000), rand_dna(rng, 70000), d0]
+    qs = [d0[:20000] + rand_dna(rng, 30000), rand_dna(rng, 70000), d0, d0[:6000],
+          rand_dna(rng, 12000)]
     data, off = queries_of(qs)
     sc, l = gix.scores(data, off)
     for i, s in enumerate(qs):
