@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--serve-pool", type=int, default=1000)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-max", type=int, default=8000)
+    ap.add_argument("--serve-streams", type=int, default=4, help="batches in flight in the server")
     ap.add_argument("--tuning", type=str, default="",
                     help="'unroll,chunk' launch shape instead of autotuning")
     ap.add_argument("--offload-gb", type=float, default=30.0,
@@ -125,7 +126,7 @@ def committed_traffic(workload: str):
         return None
 
 
-def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, plain_n):
+def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, plain_n, streams):
     """Served latency and throughput on the resident index: Poisson arrivals at
     each rate (open loop, native submitter), query lengths log-uniform in
     [31, 10^6] bp, half planted; beside it the plain path (one query per
@@ -137,7 +138,8 @@ def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, pl
     log(f"serving pool: {pool_n} queries, {pool.bytes.size / 1e6:.1f} MB ({time.time() - t0:.1f}s)")
     k = w5.k
     out = {"workload": "serve-100k: compact-100k index resident, queries log-uniform "
-                       "[31, 1e6] bp, 50% planted, Poisson arrivals", "rates": []}
+                       "[31, 1e6] bp, 50% planted, Poisson arrivals", "streams": streams,
+           "rates": []}
     # plain path: closed loop, one query per launch
     sub = pool.subset(range(min(plain_n, pool_n)))
     lat = []
@@ -175,7 +177,7 @@ def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, pl
 
     for rate in rates:
         n = int(min(max_req, max(rate * per_rate_s, 200)))
-        rec = {"rate_qps": rate, **replay(n, rate, num_streams=4)}
+        rec = {"rate_qps": rate, **replay(n, rate, num_streams=streams)}
         rec["vs_plain_throughput"] = rec["queries_per_s"] / plain["queries_per_s"]
         # the plain path served: one query per launch, first come first served;
         # beyond its capacity the queue only grows, so fewer requests are sent
@@ -343,7 +345,7 @@ def main():
     if args.serve_rates and args.config == 3:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         serving = serve_measure(cobs, synth, torch, ix, rates, args.serve_pool,
-                                args.serve_seconds, args.serve_max, 100)
+                                args.serve_seconds, args.serve_max, 100, args.serve_streams)
 
     cpu = None
     if not args.no_cpu_baseline:
