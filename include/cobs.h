@@ -23,7 +23,8 @@
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls that
  *    return host results synchronise that stream before returning.
  *  - All device memory is HBM of the current HIP device at the time of the
- *    call that creates the object; later calls must run on the same device.
+ *    call that creates the object (an offloaded matrix is pinned host
+ *    memory); later calls must run on the same device.
  *  - Scores are integers; nothing on the path uses floating point except the
  *    one-time filter sizing on the host.
  */
@@ -41,7 +42,7 @@ typedef enum {
     COBS_OK = 0,
     COBS_EINVAL = 1,      /* malformed argument */
     COBS_ENOMEM = 2,      /* device or host allocation failed */
-    COBS_EBUDGET = 3,     /* request can never fit the serving memory budget */
+    COBS_EBUDGET = 3,     /* does not fit a memory budget (serving, out-of-core) */
     COBS_EOVERFLOW = 4,   /* a query's distinct terms exceed the score width */
     COBS_EDEVICE = 5,     /* a HIP runtime call failed */
     COBS_ECANCELLED = 6,  /* the server stopped before the request ran */
@@ -165,6 +166,7 @@ cobs_status cobs_index_info(const cobs_index *ix, cobs_index_info_t *info);
  * ESTATE when the matrix already is where it would be moved; ENOMEM; EDEVICE.
  */
 cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes);
+cobs_status cobs_index_onload(cobs_index *ix);
 
 /*
  * Index files (section 2.3: an index is written once and queried many times,
@@ -189,7 +191,6 @@ cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes);
 cobs_status cobs_index_save(const cobs_index *ix, const char *path);
 cobs_status cobs_index_load(const char *path, int device, uint64_t device_budget_bytes,
                             cobs_index **out);
-cobs_status cobs_index_onload(cobs_index *ix);
 /* Block b: first sorted position, documents, rows m_b, row stride (bytes),
  * byte offset of the block inside the matrix. */
 cobs_status cobs_index_block(const cobs_index *ix, uint32_t b, uint32_t *first,
