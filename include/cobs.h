@@ -181,9 +181,9 @@ cobs_status cobs_index_onload(cobs_index *ix);
  *   matrix    total_bytes: the blocks one after another, each at its offset,
  *             rows of stride bytes, document j of a block at bit j % 8 of
  *             byte j / 8 (the device layout)
- * cobs_index_load checks the magic, the parameters, the checksum and that
- * the order and block table follow from the stored counts (EINVAL
- * otherwise).  device_budget_bytes = 0 puts the matrix in device memory of
+ * cobs_index_load checks the magic, the parameters, the checksum, that the
+ * order is a permutation and that the block table follows from the stored
+ * counts and block sizes (EINVAL otherwise).  device_budget_bytes = 0 puts the matrix in device memory of
  * `device`; otherwise it stays in pinned host memory and queries stream it as
  * after cobs_index_offload with that budget.  The caller owns *out
  * (cobs_index_free).  Errors: EINVAL (I/O, format), EBUDGET, ENOMEM, EDEVICE.
@@ -191,6 +191,20 @@ cobs_status cobs_index_onload(cobs_index *ix);
 cobs_status cobs_index_save(const cobs_index *ix, const char *path);
 cobs_status cobs_index_load(const char *path, int device, uint64_t device_budget_bytes,
                             cobs_index **out);
+/*
+ * Merge two indexes with identical parameters into a new one (section 2.3:
+ * classic indexes with the same parameters concatenate; a compact index is
+ * a concatenation of subindices).  The result's documents are a's, then
+ * b's with input ids shifted by a's n_docs.  Classic: both must have the
+ * same row count; every row is a's row followed by b's.  Compact: a's blocks
+ * followed by b's, each keeping its documents and row count (documents are
+ * not re-sorted across the two, so the result is the incremental
+ * augmentation of a by b).  Every document keeps the score it has in its
+ * own index.  Both matrices must be in device memory; the caller owns *out.
+ * Errors: EINVAL (parameters, row counts), ESTATE (offloaded input), ENOMEM,
+ * EDEVICE.
+ */
+cobs_status cobs_index_merge(const cobs_index *a, const cobs_index *b, cobs_index **out);
 /* Block b: first sorted position, documents, rows m_b, row stride (bytes),
  * byte offset of the block inside the matrix. */
 cobs_status cobs_index_block(const cobs_index *ix, uint32_t b, uint32_t *first,

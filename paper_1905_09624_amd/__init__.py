@@ -96,6 +96,7 @@ EXPORTS = {
                                    C.c_void_p, C.c_void_p]),
     "cobs_index_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cobs_index_read": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p]),
+    "cobs_index_merge": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "cobs_index_save": (C.c_int, [C.c_void_p, C.c_char_p]),
     "cobs_index_load": (C.c_int, [C.c_char_p, C.c_int, C.c_uint64, C.POINTER(C.c_void_p)]),
     "cobs_index_offload": (C.c_int, [C.c_void_p, C.c_uint64]),
@@ -216,6 +217,12 @@ class Index:
         h = C.c_void_p()
         _check(lib().cobs_index_load(os.fsencode(path), device, device_budget_bytes, C.byref(h)))
         return cls(h)
+
+    def merge(self, other: "Index") -> "Index":
+        """A new index: this one's documents, then other's (cobs_index_merge)."""
+        h = C.c_void_p()
+        _check(lib().cobs_index_merge(self._h, other._h, C.byref(h)))
+        return Index(h)
 
     def save(self, path: str) -> None:
         """Write the index to a file (cobs_index_save)."""

@@ -164,4 +164,10 @@ hipError_t launch_insert(const uint8_t *bytes, const StrDesc *strs, uint32_t n_s
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st);
 
+// Classic merge: every row of out (out_stride bytes) = the na document bits
+// of a's row, then b's row bits; strides are multiples of 4.
+hipError_t launch_concat_rows(const uint8_t *a, uint64_t a_stride, uint32_t na, const uint8_t *b,
+                              uint64_t b_stride, uint8_t *out, uint64_t out_stride, uint64_t rows,
+                              hipStream_t st);
+
 }  // namespace cobs

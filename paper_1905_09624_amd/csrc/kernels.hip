@@ -957,6 +957,32 @@ __global__ __launch_bounds__(256) void insert_kernel(const uint8_t *bytes, const
     }
 }
 
+// Row r of a merged classic index: the na document bits of a's row r, then
+// the bits of b's row r (padding bits beyond a row's documents are zero).
+__global__ void concat_rows_kernel(const uint32_t *a, uint64_t a_words, uint32_t na,
+                                   const uint32_t *b, uint64_t b_words, uint32_t *out,
+                                   uint64_t out_words, uint64_t rows)
+{
+    const uint64_t total = rows * out_words;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const uint64_t r = i / out_words, w = i - r * out_words;
+        const uint32_t *ar = a + r * a_words, *br = b + r * b_words;
+        // 32 bits of b's row from bit k >= 0
+        auto b_bits = [&](uint64_t k) -> uint32_t {
+            const uint64_t q = k >> 5;
+            const uint32_t sh = (uint32_t)(k & 31);
+            const uint32_t lo = q < b_words ? br[q] : 0u;
+            const uint32_t hi = q + 1 < b_words ? br[q + 1] : 0u;
+            return sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
+        };
+        const uint64_t j0 = 32 * w;   // first document of this output word
+        uint32_t v = j0 < na ? ar[w] : 0u;
+        if (j0 + 32 > na) v |= j0 >= na ? b_bits(j0 - na) : b_bits(0) << (uint32_t)(na - j0);
+        out[i] = v;
+    }
+}
+
 __global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1162,6 +1188,18 @@ hipError_t launch_insert(const uint8_t *bytes, const StrDesc *strs, uint32_t n_s
     if (W == 0) return hipSuccess;
     hipLaunchKernelGGL(insert_kernel, dim3(grid_for(W, 256)), dim3(256), 0, st, bytes, strs, n_strs,
                        W, pos, matrix, ts, seeds);
+    return hipGetLastError();
+}
+
+hipError_t launch_concat_rows(const uint8_t *a, uint64_t a_stride, uint32_t na, const uint8_t *b,
+                              uint64_t b_stride, uint8_t *out, uint64_t out_stride, uint64_t rows,
+                              hipStream_t st)
+{
+    const uint64_t total = rows * (out_stride / 4);
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(concat_rows_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st,
+                       (const uint32_t *)a, a_stride / 4, na, (const uint32_t *)b, b_stride / 4,
+                       (uint32_t *)out, out_stride / 4, rows);
     return hipGetLastError();
 }
 

@@ -380,30 +380,24 @@ cobs_status cobs_builder_count(cobs_builder *b, const cobs_docs *run, uint32_t f
 
 namespace {
 
-// The index layout from the documents' distinct-term counts (ix->prm,
-// n_docs, n_terms set): compact order sorted by (distinct terms, input id)
-// (sections 2.2, 2.3), blocks with their row counts, padded rows, column
-// slices and score-buffer offsets.  Host only.
-cobs_status make_layout(cobs_index *ix)
+// The index layout for a given order and block sizes (ix->prm, n_docs,
+// n_terms, order set): each block's row count from its largest distinct-term
+// count, padded rows, column slices and score-buffer offsets.  Host only.
+cobs_status layout_blocks(cobs_index *ix, const std::vector<uint32_t> &block_docs)
 {
-    const uint32_t n = ix->n_docs, B = ix->prm.block_docs;
     ix->seeds = make_seeds(ix->prm.seed);
-    ix->order.resize(n);
-    std::iota(ix->order.begin(), ix->order.end(), 0u);
-    if (B) {
-        std::stable_sort(ix->order.begin(), ix->order.end(), [&](uint32_t x, uint32_t y) {
-            return ix->n_terms[x] < ix->n_terms[y];
-        });
-    }
     ix->blocks.clear();
     ix->slices.clear();
     ix->acc_words = 0;
-    const uint32_t nb = n == 0 ? 0 : (B ? (n + B - 1) / B : 1);
     uint64_t off = 0;
-    for (uint32_t k = 0; k < nb; ++k) {
+    uint32_t first = 0;
+    for (uint32_t k = 0; k < block_docs.size(); ++k) {
         Block blk{};
-        blk.first = B ? k * B : 0;
-        blk.docs = B ? std::min(B, n - blk.first) : n;
+        blk.first = first;
+        blk.docs = block_docs[k];
+        if (blk.docs == 0 || (uint64_t)first + blk.docs > ix->n_docs)
+            return set_error(COBS_EINVAL, "block sizes do not cover the documents");
+        first += blk.docs;
         for (uint32_t j = 0; j < blk.docs; ++j)
             blk.nmax = std::max(blk.nmax, ix->n_terms[ix->order[blk.first + j]]);
         blk.rows = filter_rows(blk.nmax, ix->prm.num_hashes, ix->prm.fpr);
@@ -429,9 +423,28 @@ cobs_status make_layout(cobs_index *ix)
             ix->slices.push_back(sd);
         }
     }
+    if (first != ix->n_docs) return set_error(COBS_EINVAL, "block sizes do not cover the documents");
     if (ix->acc_words > 0xFFFFFFFFull) return set_error(COBS_EINVAL, "too many documents for one index");
     ix->total_bytes = off;
     return COBS_OK;
+}
+
+// The layout a build gives (ix->prm, n_docs, n_terms set): compact order
+// sorted by (distinct terms, input id) (sections 2.2, 2.3) and blocks of B,
+// the last one possibly partial; classic: input order, one block.
+cobs_status make_layout(cobs_index *ix)
+{
+    const uint32_t n = ix->n_docs, B = ix->prm.block_docs;
+    ix->order.resize(n);
+    std::iota(ix->order.begin(), ix->order.end(), 0u);
+    if (B) {
+        std::stable_sort(ix->order.begin(), ix->order.end(), [&](uint32_t x, uint32_t y) {
+            return ix->n_terms[x] < ix->n_terms[y];
+        });
+    }
+    std::vector<uint32_t> sizes;
+    for (uint32_t f = 0; f < n; f += B ? B : n) sizes.push_back(B ? std::min(B, n - f) : n);
+    return layout_blocks(ix, sizes);
 }
 
 // Device copies of the order and the slice table.
@@ -808,9 +821,21 @@ cobs_status cobs_index_load(const char *path, int device, uint64_t device_budget
     fnv = fnv1a(fnv, ix->n_terms.data(), ix->n_terms.size() * 8);
     fnv = fnv1a(fnv, fb.data(), fb.size() * sizeof(FileBlock));
     if (fnv != h.meta_fnv) return bad("metadata checksum mismatch");
-    // the layout follows from the counts: recompute it and insist on agreement
-    if ((s = make_layout(ix.get())) != COBS_OK) return s;
-    if (ix->order != order || ix->blocks.size() != fb.size() || ix->total_bytes != h.total_bytes)
+    // the order must be a permutation; the block table must follow from the
+    // counts and the block sizes (a merged compact index need not be sorted
+    // across its parts, section 2.3)
+    {
+        std::vector<uint8_t> seen(h.n_docs, 0);
+        for (uint32_t d : order) {
+            if (d >= h.n_docs || seen[d]) return bad("order is not a permutation");
+            seen[d] = 1;
+        }
+    }
+    ix->order = order;
+    std::vector<uint32_t> sizes;
+    for (const FileBlock &b : fb) sizes.push_back(b.docs);
+    if ((s = layout_blocks(ix.get(), sizes)) != COBS_OK) return bad("invalid block table");
+    if (ix->blocks.size() != fb.size() || ix->total_bytes != h.total_bytes)
         return bad("layout does not follow from the stored counts");
     for (size_t b = 0; b < fb.size(); ++b) {
         const Block &k = ix->blocks[b];
@@ -850,6 +875,77 @@ cobs_status cobs_index_load(const char *path, int device, uint64_t device_budget
         }
     }
     COBS_HIP(hipDeviceSynchronize());
+    *out = ix.release();
+    return COBS_OK;
+}
+
+cobs_status cobs_index_merge(const cobs_index *a, const cobs_index *b, cobs_index **out)
+{
+    if (!a || !b || !out) return set_error(COBS_EINVAL, "NULL argument");
+    *out = nullptr;
+    const cobs_params &p = a->prm, &q = b->prm;
+    if (p.kind != q.kind || p.q != q.q || p.canonical != q.canonical || p.num_hashes != q.num_hashes ||
+        p.fpr != q.fpr || p.block_docs != q.block_docs || p.seed != q.seed)
+        return set_error(COBS_EINVAL, "indexes with different parameters");
+    if (a->device != b->device) return set_error(COBS_EINVAL, "indexes on different devices");
+    if (a->h_matrix || b->h_matrix) return set_error(COBS_ESTATE, "merge needs both matrices in device memory");
+    if ((uint64_t)a->n_docs + b->n_docs > 0xFFFFFFFFull) return set_error(COBS_EINVAL, "too many documents");
+    const bool classic = p.block_docs == 0;
+    if (classic && a->n_docs && b->n_docs && a->blocks[0].rows != b->blocks[0].rows)
+        return set_error(COBS_EINVAL, "classic indexes merge only with equal row counts (" +
+                                          std::to_string(a->blocks[0].rows) + " and " +
+                                          std::to_string(b->blocks[0].rows) + ")");
+    COBS_HIP(hipSetDevice(a->device));
+    std::unique_ptr<cobs_index> ix(new cobs_index());
+    ix->prm = p;
+    ix->device = a->device;
+    const uint32_t na = a->n_docs;
+    ix->n_docs = na + b->n_docs;
+    ix->n_terms = a->n_terms;
+    ix->n_terms.insert(ix->n_terms.end(), b->n_terms.begin(), b->n_terms.end());
+    ix->order = a->order;
+    for (uint32_t d : b->order) ix->order.push_back(d + na);
+    std::vector<uint32_t> sizes;
+    if (classic) {
+        if (ix->n_docs) sizes.push_back(ix->n_docs);
+    } else {
+        for (const Block &k : a->blocks) sizes.push_back(k.docs);
+        for (const Block &k : b->blocks) sizes.push_back(k.docs);
+    }
+    cobs_status s = layout_blocks(ix.get(), sizes);
+    if (s != COBS_OK) return s;
+    hipStream_t st = nullptr;
+    if (ix->total_bytes) {
+        hipError_t e = hipMalloc(&ix->d_matrix, ix->total_bytes);
+        if (e != hipSuccess) {
+            ix->d_matrix = nullptr;
+            return set_error(COBS_ENOMEM, "device memory for the matrix");
+        }
+    }
+    if (classic && ix->n_docs) {
+        const Block &o = ix->blocks[0];
+        const cobs_index *x = na ? a : b;   // a side with documents gives the row count
+        if (o.rows != x->blocks[0].rows) return set_error(COBS_EINVAL, "row counts disagree");
+        if (na && b->n_docs) {
+            COBS_HIP(launch_concat_rows(a->d_matrix, a->blocks[0].stride, na, b->d_matrix,
+                                        b->blocks[0].stride, ix->d_matrix, o.stride, o.rows, st));
+        } else {
+            COBS_HIP(hipMemcpyAsync(ix->d_matrix, x->d_matrix, x->total_bytes, hipMemcpyDeviceToDevice, st));
+        }
+    } else if (!classic) {
+        size_t k = 0;
+        for (const cobs_index *x : {a, b}) {
+            for (const Block &src : x->blocks) {
+                const Block &dst = ix->blocks[k++];
+                if (dst.rows != src.rows || dst.stride != src.stride)
+                    return set_error(COBS_EINVAL, "block layout disagrees");
+                COBS_HIP(hipMemcpyAsync(ix->d_matrix + dst.offset, x->d_matrix + src.offset,
+                                        src.rows * src.stride, hipMemcpyDeviceToDevice, st));
+            }
+        }
+    }
+    if ((s = upload_layout(ix.get(), st)) != COBS_OK) return s;
+    COBS_HIP(hipStreamSynchronize(st));
     *out = ix.release();
     return COBS_OK;
 }
