@@ -102,6 +102,40 @@ typedef struct cobs_index cobs_index;
 typedef struct cobs_builder cobs_builder;
 typedef struct cobs_server cobs_server;
 
+/* ---- documents from files (section 2.3) ---------------------------------- */
+
+/*
+ * Host-side document collection built from files in the formats the paper
+ * reads.  Each call appends documents:
+ *  COBS_FORMAT_FASTA        one document; each record ('>' header, then the
+ *                           sequence lines, whitespace dropped) is one string,
+ *                           so reads are hashed independently; ';' lines are
+ *                           comments
+ *  COBS_FORMAT_MULTI_FASTA  one document per record (one string each)
+ *  COBS_FORMAT_FASTQ        one document; each four-line read ('@' header,
+ *                           sequence, '+' line, quality of equal length) is one
+ *                           string; EINVAL for a malformed or truncated record
+ *                           (nothing of the file is kept)
+ *  COBS_FORMAT_TEXT         one document: the whole file as one continuous
+ *                           string
+ * cobs_docset_view fills a host cobs_docs (for cobs_build or the builder, or
+ * as query strings) that stays valid until the next append or the free.
+ */
+typedef enum {
+    COBS_FORMAT_FASTA = 0,
+    COBS_FORMAT_MULTI_FASTA = 1,
+    COBS_FORMAT_FASTQ = 2,
+    COBS_FORMAT_TEXT = 3
+} cobs_format;
+
+typedef struct cobs_docset cobs_docset;
+cobs_status cobs_docset_create(cobs_docset **out);
+cobs_status cobs_docset_add_file(cobs_docset *ds, const char *path, uint32_t format);
+cobs_status cobs_docset_add_buffer(cobs_docset *ds, const uint8_t *data, uint64_t len,
+                                   uint32_t format);
+cobs_status cobs_docset_view(const cobs_docset *ds, cobs_docs *docs);
+void cobs_docset_free(cobs_docset *ds);
+
 /* ---- construction (sections 2.1-2.3) ------------------------------------ */
 
 /*

@@ -97,6 +97,11 @@ EXPORTS = {
     "cobs_index_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cobs_index_read": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p]),
     "cobs_index_merge": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "cobs_docset_create": (C.c_int, [C.POINTER(C.c_void_p)]),
+    "cobs_docset_add_file": (C.c_int, [C.c_void_p, C.c_char_p, C.c_uint32]),
+    "cobs_docset_add_buffer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32]),
+    "cobs_docset_view": (C.c_int, [C.c_void_p, C.POINTER(DocsC)]),
+    "cobs_docset_free": (None, [C.c_void_p]),
     "cobs_index_save": (C.c_int, [C.c_void_p, C.c_char_p]),
     "cobs_index_load": (C.c_int, [C.c_char_p, C.c_int, C.c_uint64, C.POINTER(C.c_void_p)]),
     "cobs_index_offload": (C.c_int, [C.c_void_p, C.c_uint64]),
@@ -190,6 +195,45 @@ def _docs_struct(data, str_off, doc_str):
     ds = np.ascontiguousarray(doc_str, dtype=np.uint64)
     d = DocsC(ptr, C.c_void_p(so.ctypes.data), C.c_void_p(ds.ctypes.data), len(ds) - 1, mem)
     return d, (keep, so, ds)
+
+
+FASTA, MULTI_FASTA, FASTQ, TEXT = range(4)
+
+
+class DocSet:
+    """Documents read from FASTA / multi-FASTA / FASTQ / text files or buffers
+    (cobs_docset_*); arrays() gives (bytes, str_off, doc_str) for Index.build
+    or as queries."""
+
+    def __init__(self):
+        self._h = C.c_void_p()
+        _check(lib().cobs_docset_create(C.byref(self._h)))
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().cobs_docset_free(self._h)
+            self._h = None
+
+    def add_file(self, path: str, fmt: int) -> "DocSet":
+        _check(lib().cobs_docset_add_file(self._h, os.fsencode(path), fmt))
+        return self
+
+    def add_buffer(self, data: bytes, fmt: int) -> "DocSet":
+        buf = np.frombuffer(data, np.uint8) if len(data) else np.zeros(1, np.uint8)
+        _check(lib().cobs_docset_add_buffer(self._h, C.c_void_p(buf.ctypes.data), len(data), fmt))
+        return self
+
+    def arrays(self):
+        d = DocsC()
+        _check(lib().cobs_docset_view(self._h, C.byref(d)))
+        n_str = 0
+        ds = np.ctypeslib.as_array(C.cast(d.doc_str, C.POINTER(C.c_uint64)), (d.n_docs + 1,)).copy()
+        n_str = int(ds[-1])
+        so = np.ctypeslib.as_array(C.cast(d.str_off, C.POINTER(C.c_uint64)), (n_str + 1,)).copy()
+        nb = int(so[-1])
+        data = (np.ctypeslib.as_array(C.cast(d.bytes, C.POINTER(C.c_uint8)), (nb,)).copy()
+                if nb else np.zeros(0, np.uint8))
+        return data, so, ds
 
 
 def make_params(kind=DNA, q=31, canonical=True, h=1, p=0.3, B=0, seed=0x5EED) -> Params:

@@ -160,6 +160,31 @@ def test_bytes_terms_with_all_ones_term():
     assert gix.order()[1][0] == 3 + 8   # distinct 8-grams of the document
 
 
+def test_index_from_fasta_files_with_many_reads(tmp_path):
+    # documents read from FASTA files: every read is a string of its document
+    # (no k-mer spans two reads); the index and hits equal the oracle's over
+    # the same strings, and multi-FASTA query files give one query per record
+    cobs = _cobs()
+    rng = np.random.default_rng(13)
+    ds = cobs.DocSet()
+    for d in range(9):
+        reads = [rand_dna(rng, int(rng.integers(20, 400)), b"ACGTacgtN") for _ in range(int(rng.integers(1, 30)))]
+        path = tmp_path / f"doc{d}.fa"
+        path.write_bytes(b"".join(b">r%d\n%s\n" % (i, r) for i, r in enumerate(reads)))
+        ds.add_file(str(path), cobs.FASTA)
+    data, so, dstr = ds.arrays()
+    docs = oracle.Docs(data, so, dstr)
+    gix, oix = build_both(docs, 0, 15, True, 2, 0.2, 4, 5)
+    assert_same_index(gix, oix)
+    picks = [data[int(so[s]):int(so[s + 1])].tobytes() for s in (0, 3, 7, 20)]
+    qfile = tmp_path / "queries.fa"
+    qfile.write_bytes(b"".join(b">q%d\n%s\n" % (i, q) for i, q in enumerate(picks)))
+    qd, qso, qds = cobs.DocSet().add_file(str(qfile), cobs.MULTI_FASTA).arrays()
+    assert len(qds) == len(picks) + 1
+    check_queries(gix, oix, qd, qso, k=(1, 2), topk=0)
+    check_queries(gix, oix, qd, qso, k=(0, 1), topk=3, mode=1)
+
+
 # ---- scores and hits on scaled workloads -------------------------------------------
 
 WORKLOADS = {
