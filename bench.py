@@ -189,35 +189,44 @@ def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, pl
 
 
 def cpu_baseline(w, synth, oracle, qs, budget_s):
-    """The CPU oracle on a bounded sample: documents 0..S-1 of the workload
-    (their own compact plan), the first queries of the set; lookups/s scaled
-    from S documents to the workload's document count."""
+    """The CPU oracle on bounded samples: the S smallest documents of the
+    workload (their own compact plan), for S = 32 and 256, queried with the
+    query set (cycled) for half the budget each.  The time per lookup is
+    a + b * S (a per lookup: terms, hashing; b per document); the rate is
+    extrapolated to the workload's document count along that line."""
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
-    S = 32 if w.n_docs >= 32 else w.n_docs
-    sub = synth.dna_docs(w, first=0, count=S) if w.kind == "dna" else None
-    if sub is None:
+    if w.kind != "dna" or w.n_docs < 256:
         return None
-    kind = oracle.DNA
-    ix = oracle.OracleIndex(oracle.Docs(sub.bytes, sub.str_off, sub.doc_str), kind=kind, q=w.q,
-                            canonical=w.canonical, h=w.h, p=w.p, B=min(w.B, S) if w.B else 0,
-                            seed=w.hash_seed)
-    threads = os.cpu_count() or 1
-    threads = min(threads, 16)
-    done_l, t0 = 0, time.perf_counter()
-    i, nq = 0, qs.n
-    with ThreadPoolExecutor(threads) as ex:
-        while time.perf_counter() - t0 < budget_s:
-            batch = [qs.get(j % nq) for j in range(i, i + 4 * threads)]
-            for sc, l in ex.map(ix.query_scores, batch):
-                done_l += l
-            i += len(batch)
-    dt = time.perf_counter() - t0
-    rate = done_l * S / dt / w.n_docs
+    smallest = np.argsort(synth.doc_lengths(w), kind="stable")
+    threads = min(os.cpu_count() or 1, 16)
+    points, notes = [], []
+    for S in (32, 256):
+        texts = [synth.dna_docs(w, first=int(d), count=1).bytes.tobytes() for d in smallest[:S]]
+        ix = oracle.OracleIndex(oracle.Docs.from_lists(texts), kind=oracle.DNA, q=w.q,
+                                canonical=w.canonical, h=w.h, p=w.p, B=min(w.B, S) if w.B else 0,
+                                seed=w.hash_seed)
+        done_l, i, nq = 0, 0, qs.n
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            while time.perf_counter() - t0 < budget_s / 2:
+                batch = [qs.get(j % nq) for j in range(i, i + 4 * threads)]
+                for sc, l in ex.map(ix.query_scores, batch):
+                    done_l += l
+                i += len(batch)
+        dt = time.perf_counter() - t0
+        points.append((S, dt / done_l))
+        notes.append(f"{S} docs: {i} queries, {done_l / dt:.3g} lookups/s")
+        del ix
+    (s0, t0_), (s1, t1_) = points
+    b = max((t1_ - t0_) / (s1 - s0), 0.0)
+    a = max(t0_ - b * s0, 0.0)
+    rate = 1.0 / (a + b * w.n_docs)
     return {"value": rate, "unit": "lookups/s", "cores": threads, "kind": "oracle",
-            "sample": f"{i} queries (the set, cycled) against documents 0..{S - 1} (their own "
-                      f"{'compact' if w.B else 'classic'} plan), {dt:.1f}s wall; "
-                      f"rate scaled by {S}/{w.n_docs} documents"}
+            "sample": f"the 32 and 256 smallest documents (their own compact plan), the query "
+                      f"set cycled, {budget_s / 2:.0f}s each ({'; '.join(notes)}); time per "
+                      f"lookup {a * 1e9:.0f} ns + {b * 1e9:.2f} ns per document, extrapolated "
+                      f"to {w.n_docs} documents"}
 
 
 def main():
