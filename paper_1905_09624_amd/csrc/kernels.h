@@ -78,7 +78,7 @@ struct GatherArgs {
     const uint32_t *qorder;            // [n_queries] work order of the queries
     const uint32_t *chunk_prefix;      // [n_queries + 1], in qorder order
     unsigned long long *work_counter;  // device scalar, zero at launch; items = chunks x n_slices
-    uint32_t *tickets;                 // [n_queries * n_slices]
+    uint32_t *tickets;                 // [n_queries * n_slices], zero; left zero by every launch
     uint32_t *accum;                   // score buffers of split queries (zero between launches)
     uint64_t acc_words;                // words per score buffer
     unsigned long long *cand_counter;  // device scalar
@@ -118,9 +118,6 @@ bool dedup_small_table(uint64_t windows);      // LDS table of kLdsTableSlots / 
 uint64_t dedup_table_cap(uint64_t windows);    // hash-set capacity for a query (power of 2)
 uint64_t dedup_table_slots(uint64_t windows);  // global slots (0: LDS table)
 uint32_t dedup_groups(uint64_t windows);       // workgroups of the query
-// tickets: [n_queries * n_slices], zero before the first gather; every
-// complete gather launch leaves them zero again.
-
 // Per-query chunks, thresholds, score-buffer slots, work totals; zeroes
 // counters.  qorder: the queries by size class, largest first (work items
 // follow that order); chunk_prefix[i]: first chunk of query qorder[i].  A query split into several chunks uses score buffer slot[i] when

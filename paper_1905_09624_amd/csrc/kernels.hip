@@ -4,11 +4,11 @@
 //   extract  -- one q-gram per window (section 2.1), canonical k-mers (2.3)
 //   dedup    -- the query's term set G_q(P), l = |G_q(P)|, h hashes per term
 //   plan     -- per-query term chunks, threshold T = ceil(K l)
-//   gather   -- persistent wavefronts: for each (query, column slice, chunk)
+//   gather   -- persistent wavefronts: for each (query chunk, column slice)
 //               fetch the h rows of every term (one coalesced 1 KiB line per
 //               row slice), AND them, add the surviving bits into bit-plane
-//               counters held in VGPRs; merge chunk partials; threshold or
-//               per-slice top-k; emit candidates
+//               counters held in VGPRs; split queries merge their counts in a
+//               score buffer; threshold or per-slice top-k; emit candidates
 //   group/sort -- order each query's hits by (score desc, input id asc)
 // Construction (sections 2.1-2.3): exact distinct-term counts per document
 // (hash-set), then one atomic OR per (term, hash) into the padded matrix.

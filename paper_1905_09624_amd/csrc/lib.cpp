@@ -1089,7 +1089,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     const uint64_t nbytes = b.q_off[n] - b.q_off[0];
     if (nbytes && !b.bytes) return set_error(COBS_EINVAL, "bytes is NULL");
 
-    // host plan: windows, tables, partial-slot bound
+    // host plan: windows, dedup tables, launch shape, score-buffer slots
     std::vector<uint64_t> hv(2 * (size_t)n + 1);
     uint64_t *qstart = hv.data(), *wbase = hv.data() + n;
     uint64_t W = 0, maxw = 0, tslots = 0;
