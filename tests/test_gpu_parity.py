@@ -286,6 +286,24 @@ def test_long_query_multi_chunk_and_global_table():
             assert res[i][2] == l and np.array_equal(res[i][0], ids) and np.array_equal(res[i][1], sc)
 
 
+def test_very_long_queries_use_wide_counters():
+    # 1.1 M and 16.8 M distinct terms: 24 and 32 counter planes, dedup over
+    # many workgroups, thousands of chunks per (query, slice)
+    rng = np.random.default_rng(31)
+    docs = oracle.Docs.from_lists([rand_dna(rng, int(n)) for n in rng.integers(20000, 60000, 10)])
+    gix, oix = build_both(docs, 0, 31, True, 1, 0.3, 4, 9)
+    d0 = docs.bytes[int(docs.str_off[0]):int(docs.str_off[1])].tobytes()
+    qs = [d0 + rand_dna(rng, 1_100_000), rand_dna(rng, (1 << 24) + 200_000)]
+    data, off = queries_of(qs)
+    sc, l = gix.scores(data, off)
+    hits = gix.query(data, off, k=(1, 100), topk=3)
+    for i, q in enumerate(qs):
+        want, wl = oix.query_scores(q)
+        assert l[i] == wl and np.array_equal(sc[i], want), i
+        ids, scores = oracle.report(want, wl, 1, 100, 3)
+        assert np.array_equal(hits[i][0], ids) and np.array_equal(hits[i][1], scores), i
+
+
 @pytest.mark.parametrize("unroll,chunk", [(4, 32), (8, 100), (4, 1024), (8, 7), (8, 1 << 20)])
 def test_launch_shapes_give_identical_results(workload, unroll, chunk):
     # every instantiated unroll and several term-chunk sizes (many merges at
