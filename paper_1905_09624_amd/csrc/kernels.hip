@@ -172,26 +172,28 @@ __host__ __device__ __forceinline__ uint64_t table_cap(uint64_t n)
 
 // ---- a1: term extraction ------------------------------------------------------
 
-// Each wavefront takes tiles of 64 x kExtractPerLane consecutive windows
+// Each wavefront takes tiles of 64 x per_lane consecutive windows
 // (consecutive lanes, consecutive windows: coalesced term writes); the query
 // of a tile's first window is found by one binary search, later windows
-// advance from it.
+// advance from it.  per_lane is 16 for large batches and shrinks for small
+// ones, so that a short query still spreads over several wavefronts.
 constexpr uint32_t kExtractPerLane = 16;
 
 __global__ __launch_bounds__(256) void extract_kernel(const uint8_t *bytes, const uint64_t *qstart,
                                                       const uint64_t *wbase, uint32_t n, uint64_t W,
-                                                      TermSpec ts, uint64_t *terms, uint32_t *nterms)
+                                                      uint32_t per_lane, TermSpec ts, uint64_t *terms,
+                                                      uint32_t *nterms)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         nterms[i] = 0;
     const uint32_t lane = lane_id();
-    const uint64_t tile = 64ull * kExtractPerLane;
+    const uint64_t tile = 64ull * per_lane;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t waves = stride >> 6;
     for (uint64_t t0 = wave * tile; t0 < W; t0 += waves * tile) {
         uint32_t qi = bsearch_le(wbase, n, t0);
-        for (uint32_t i = 0; i < kExtractPerLane; ++i) {
+        for (uint32_t i = 0; i < per_lane; ++i) {
             const uint64_t w = t0 + (uint64_t)i * 64 + lane;
             if (w >= W) break;
             while (w >= wbase[qi + 1]) ++qi;
@@ -369,6 +371,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, cons
 
     // per-query state in input order; score-buffer slots of split queries
     if (tid < 33) s_class[tid] = 0;
+    if (tid == 0) *flags = 0;
     __syncthreads();
     uint32_t sp = 0;
     for (uint32_t q = a; q < b; ++q) {
@@ -804,17 +807,37 @@ __global__ __launch_bounds__(1024) void group_scan_kernel(const uint32_t *qcount
     if (tid == nt - 1) { qstart[n] = s_a[nt - 1]; out_start[n] = s_b[nt - 1]; }
 }
 
-__global__ void group_scatter_kernel(const uint64_t *cand_key, const uint32_t *cand_q,
-                                     const unsigned long long *n_cand, uint64_t cap,
-                                     const uint32_t *qstart, uint32_t *qcursor, uint64_t *seg)
+// Candidates into their query's segment.  A wavefront's 64 candidates mostly
+// belong to one query (a wavefront emits one (query, slice) at a time), so
+// each distinct query among them takes one atomic add for all its lanes.
+__global__ __launch_bounds__(256) void group_scatter_kernel(const uint64_t *cand_key,
+                                                            const uint32_t *cand_q,
+                                                            const unsigned long long *n_cand,
+                                                            uint64_t cap, const uint32_t *qstart,
+                                                            uint32_t *qcursor, uint64_t *seg)
 {
     const uint64_t n = *n_cand;
     if (n > cap) return;   // overflow: the host enlarges the buffers and reruns
+    const uint32_t lane = lane_id();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t q = cand_q[i];
-        const uint32_t pos = qstart[q] + atomicAdd(&qcursor[q], 1u);
-        seg[pos] = cand_key[i];
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n;
+         base += stride) {
+        const uint64_t i = base + lane;
+        const bool valid = i < n;
+        const uint32_t q = valid ? cand_q[i] : 0u;
+        uint64_t todo = __ballot(valid);
+        uint64_t pos = 0;
+        while (todo) {
+            const uint32_t leader = (uint32_t)__builtin_ctzll(todo);
+            const uint32_t ql = lane_u32(q, leader);
+            const uint64_t m = __ballot(valid && q == ql) & todo;
+            uint32_t b0 = 0;
+            if (lane == leader) b0 = atomicAdd(&qcursor[ql], (uint32_t)__popcll(m));
+            b0 = lane_u32(b0, leader);
+            if ((m >> lane) & 1ull) pos = (uint64_t)qstart[ql] + b0 + __popcll(m & ((1ull << lane) - 1ull));
+            todo &= ~m;
+        }
+        if (valid) seg[pos] = cand_key[i];
     }
 }
 
@@ -1044,10 +1067,13 @@ hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const ui
                           uint32_t *nterms, hipStream_t st)
 {
     if (n_queries == 0) return hipSuccess;
-    const uint64_t tiles = (W + 64ull * kExtractPerLane - 1) / (64ull * kExtractPerLane);
+    // about 8192 wavefronts' worth of tiles, 1 to kExtractPerLane windows per lane
+    const uint32_t per_lane = (uint32_t)std::min<uint64_t>(
+        kExtractPerLane, std::max<uint64_t>(1, W / (64ull * 8192)));
+    const uint64_t tiles = (W + 64ull * per_lane - 1) / (64ull * per_lane);
     hipLaunchKernelGGL(extract_kernel,
                        dim3(grid_for(std::max<uint64_t>(tiles * 64, n_queries), 256)), dim3(256), 0,
-                       st, bytes, qstart, wbase, n_queries, W, ts, terms, nterms);
+                       st, bytes, qstart, wbase, n_queries, W, per_lane, ts, terms, nterms);
     return hipGetLastError();
 }
 
@@ -1163,8 +1189,8 @@ hipError_t launch_group_sort(const uint64_t *cand_key, const uint32_t *cand_q,
 {
     hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, st, qcount, n_queries, topk,
                        qstart, qcursor, out_start, out_n);
-    hipLaunchKernelGGL(group_scatter_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, st, cand_key,
-                       cand_q, n_cand, cap, qstart, qcursor, seg_a);
+    hipLaunchKernelGGL(group_scatter_kernel, dim3(std::min(grid_for(cap, 256), 2048)), dim3(256), 0, st,
+                       cand_key, cand_q, n_cand, cap, qstart, qcursor, seg_a);
     hipLaunchKernelGGL(segsort_kernel, dim3(n_queries), dim3(1024), 0, st, seg_a, seg_b, n_cand,
                        cap, qstart, out_start, out_n, out_id, out_score);
     return hipGetLastError();

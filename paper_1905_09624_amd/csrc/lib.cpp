@@ -1183,18 +1183,24 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     COBS_HIP(ws.terms.ensure(std::max<uint64_t>(W, 1) * 8));
     COBS_HIP(ws.uterms.ensure(std::max<uint64_t>(W, 1) * 8));
     COBS_HIP(ws.hashes.ensure(std::max<uint64_t>(W, 1) * 8 * h));
-    COBS_HIP(ws.nterms.ensure((size_t)n * 4));
+    // result head, copied back in one piece: Scalars | nterms[n] | out_n[n] | out_start[n + 1]
+    const size_t head_bytes = sizeof(Scalars) + (size_t)n * 8 + (size_t)(n + 1) * 4;
+    COBS_HIP(ws.head.ensure(head_bytes));
+    Scalars *dsc = ws.head.as<Scalars>();
+    uint32_t *d_nterms = (uint32_t *)(ws.head.as<uint8_t>() + sizeof(Scalars));
+    uint32_t *d_out_n = d_nterms + n;
+    uint32_t *d_out_start = d_out_n + n;
     COBS_HIP(ws.table.ensure(std::max<uint64_t>(tslots, 1) * 8));
-    COBS_HIP(launch_extract(dbytes, d_qstart, d_wbase, n, W, ts, ws.terms.as<uint64_t>(),
-                            ws.nterms.as<uint32_t>(), st));
+    COBS_HIP(launch_extract(dbytes, d_qstart, d_wbase, n, W, ts, ws.terms.as<uint64_t>(), d_nterms,
+                            st));
     COBS_HIP(launch_dedup(ws.terms.as<uint64_t>(), d_wbase, d_tbase, d_lds_q, n_small,
                           (uint32_t)lds_large.size(), d_g_q, d_gprefix, (uint32_t)g_q.size(),
                           (uint32_t)groups, ws.table.as<uint64_t>(), tslots,
-                          ws.uterms.as<uint64_t>(), ws.hashes.as<uint64_t>(),
-                          ws.nterms.as<uint32_t>(), ts, ix->seeds, st));
+                          ws.uterms.as<uint64_t>(), ws.hashes.as<uint64_t>(), d_nterms, ts,
+                          ix->seeds, st));
     if (b.terms_out) {
         std::vector<uint32_t> nt(n);
-        COBS_HIP(hipMemcpyAsync(nt.data(), ws.nterms.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+        COBS_HIP(hipMemcpyAsync(nt.data(), d_nterms, (size_t)n * 4, hipMemcpyDeviceToHost, st));
         if (W) COBS_HIP(hipMemcpyAsync(b.terms_out, ws.uterms.p, W * 8, hipMemcpyDeviceToHost, st));
         COBS_HIP(hipStreamSynchronize(st));
         out.num_terms = nt;
@@ -1210,7 +1216,6 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     COBS_HIP(ws.qinfo.ensure((size_t)n * sizeof(QInfo)));
     COBS_HIP(ws.chunk_prefix.ensure((size_t)(n + 1) * 4));
     COBS_HIP(ws.qorder.ensure((size_t)n * 4));
-    COBS_HIP(ws.scalars.ensure(sizeof(Scalars)));
     // score buffers of split queries: zero on allocation, left zero by every
     // complete gather launch
     uint32_t *accum = b.accum;
@@ -1223,16 +1228,14 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         accum = ws.accum.as<uint32_t>();
     }
     COBS_HIP(ws.qcount.ensure((size_t)n * 4));
-    COBS_HIP(hipMemsetAsync(ws.scalars.p, 0, sizeof(Scalars), st));
     const uint64_t ell_limit = b.score_bits == 16 ? 0xFFFFull : 0xFFFFFFFFull;
     const bool full = b.full_scores != nullptr;
     if (ws.cand_cap == 0) ws.cand_cap = std::max<uint64_t>(1 << 20, (uint64_t)n * 64);
-    Scalars *dsc = ws.scalars.as<Scalars>();
 
     for (int attempt = 0;; ++attempt) {
         COBS_HIP(ws.cand_key.ensure(ws.cand_cap * 8));
         COBS_HIP(ws.cand_q.ensure(ws.cand_cap * 4));
-        COBS_HIP(launch_plan(ws.nterms.as<uint32_t>(), d_wbase, d_slot, n, C, n_slices,
+        COBS_HIP(launch_plan(d_nterms, d_wbase, d_slot, n, C, n_slices,
                              b.k_num, b.k_den, ell_limit, ws.qinfo.as<QInfo>(),
                              ws.qorder.as<uint32_t>(), ws.chunk_prefix.as<uint32_t>(),
                              &dsc->total_items, &dsc->work_counter, &dsc->cand_counter,
@@ -1296,13 +1299,16 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
             return COBS_OK;
         };
         if (full) {
-            Scalars hs;
-            COBS_HIP(hipMemcpyAsync(&hs, dsc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-            COBS_HIP(hipMemcpyAsync(out.num_terms.data(), ws.nterms.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+            const size_t nb = sizeof(Scalars) + (size_t)n * 4;
+            COBS_HIP(ws.h_small.ensure(nb));
+            COBS_HIP(hipMemcpyAsync(ws.h_small.p, ws.head.p, nb, hipMemcpyDeviceToHost, st));
             if (ix->n_docs)
                 COBS_HIP(hipMemcpyAsync(b.full_scores, ws.full.p, (uint64_t)n * ix->n_docs * 4,
                                         hipMemcpyDeviceToHost, st));
             COBS_HIP(hipStreamSynchronize(st));
+            Scalars hs;
+            std::memcpy(&hs, ws.h_small.p, sizeof(Scalars));
+            std::memcpy(out.num_terms.data(), ws.h_small.as<uint8_t>() + sizeof(Scalars), (size_t)n * 4);
             if (hs.flags & 1u) return set_error(COBS_EOVERFLOW, "a query exceeds the score width");
             return account(out.num_terms.data());
         }
@@ -1310,26 +1316,17 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         COBS_HIP(ws.gcursor.ensure((size_t)n * 4));
         COBS_HIP(ws.seg_a.ensure(ws.cand_cap * 8));
         COBS_HIP(ws.seg_b.ensure(ws.cand_cap * 8));
-        COBS_HIP(ws.out_start.ensure((size_t)(n + 1) * 4));
-        COBS_HIP(ws.out_n.ensure((size_t)n * 4));
         COBS_HIP(ws.out_id.ensure(ws.cand_cap * 4));
         COBS_HIP(ws.out_score.ensure(ws.cand_cap * 4));
         COBS_HIP(launch_group_sort(ws.cand_key.as<uint64_t>(), ws.cand_q.as<uint32_t>(),
                                    &dsc->cand_counter, ws.cand_cap, n, b.topk,
                                    ws.qcount.as<uint32_t>(), ws.gstart.as<uint32_t>(),
                                    ws.gcursor.as<uint32_t>(), ws.seg_a.as<uint64_t>(),
-                                   ws.seg_b.as<uint64_t>(), ws.out_start.as<uint32_t>(),
-                                   ws.out_n.as<uint32_t>(), ws.out_id.as<uint32_t>(),
-                                   ws.out_score.as<uint32_t>(), st));
-        const size_t small = sizeof(Scalars) + (size_t)n * 4 * 2 + (size_t)(n + 1) * 4;
-        COBS_HIP(ws.h_small.ensure(small));
+                                   ws.seg_b.as<uint64_t>(), d_out_start, d_out_n,
+                                   ws.out_id.as<uint32_t>(), ws.out_score.as<uint32_t>(), st));
+        COBS_HIP(ws.h_small.ensure(head_bytes));
         uint8_t *hs = ws.h_small.as<uint8_t>();
-        COBS_HIP(hipMemcpyAsync(hs, dsc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-        COBS_HIP(hipMemcpyAsync(hs + sizeof(Scalars), ws.nterms.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
-        COBS_HIP(hipMemcpyAsync(hs + sizeof(Scalars) + (size_t)n * 4, ws.out_n.p, (size_t)n * 4,
-                                hipMemcpyDeviceToHost, st));
-        COBS_HIP(hipMemcpyAsync(hs + sizeof(Scalars) + (size_t)n * 8, ws.out_start.p,
-                                (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, st));
+        COBS_HIP(hipMemcpyAsync(hs, ws.head.p, head_bytes, hipMemcpyDeviceToHost, st));
         COBS_HIP(hipStreamSynchronize(st));
         Scalars sc;
         std::memcpy(&sc, hs, sizeof(Scalars));
@@ -1375,7 +1372,7 @@ cobs_status reserve_workspace(cobs_index *ix, Workspace &ws, uint64_t W, uint32_
     COBS_HIP(ws.terms.ensure(std::max<uint64_t>(W, 1) * 8));
     COBS_HIP(ws.uterms.ensure(std::max<uint64_t>(W, 1) * 8));
     COBS_HIP(ws.hashes.ensure(std::max<uint64_t>(W, 1) * 8 * h));
-    COBS_HIP(ws.nterms.ensure((size_t)n * 4));
+    COBS_HIP(ws.head.ensure(sizeof(Scalars) + (size_t)n * 8 + (size_t)(n + 1) * 4));
     COBS_HIP(ws.table.ensure(std::max<uint64_t>(4 * W + n, 1) * 8));
     if (ws.tickets_slots < (uint64_t)n * n_slices || !ws.tickets.p) {
         COBS_HIP(ws.tickets.ensure(std::max<uint64_t>((uint64_t)n * n_slices, 1) * 4, true, st));
@@ -1384,7 +1381,6 @@ cobs_status reserve_workspace(cobs_index *ix, Workspace &ws, uint64_t W, uint32_
     COBS_HIP(ws.qinfo.ensure((size_t)n * sizeof(QInfo)));
     COBS_HIP(ws.chunk_prefix.ensure((size_t)(n + 1) * 4));
     COBS_HIP(ws.qorder.ensure((size_t)n * 4));
-    COBS_HIP(ws.scalars.ensure(sizeof(Scalars)));
     COBS_HIP(ws.qcount.ensure((size_t)n * 4));
     ws.cand_cap = std::max<uint64_t>(ws.cand_cap, std::max<uint64_t>(1 << 20, (uint64_t)n * 64));
     COBS_HIP(ws.cand_key.ensure(ws.cand_cap * 8));
@@ -1393,8 +1389,6 @@ cobs_status reserve_workspace(cobs_index *ix, Workspace &ws, uint64_t W, uint32_
     COBS_HIP(ws.gcursor.ensure((size_t)n * 4));
     COBS_HIP(ws.seg_a.ensure(ws.cand_cap * 8));
     COBS_HIP(ws.seg_b.ensure(ws.cand_cap * 8));
-    COBS_HIP(ws.out_start.ensure((size_t)(n + 1) * 4));
-    COBS_HIP(ws.out_n.ensure((size_t)n * 4));
     COBS_HIP(ws.out_id.ensure(ws.cand_cap * 4));
     COBS_HIP(ws.out_score.ensure(ws.cand_cap * 4));
     COBS_HIP(ws.h_small.ensure(sizeof(Scalars) + (size_t)n * 8 + (size_t)(n + 1) * 4));

@@ -56,10 +56,10 @@ struct Block {
 
 // Everything one query batch needs on the device; reused across batches.
 struct Workspace {
-    DevBuf bytes, meta, terms, uterms, hashes, nterms, table;
-    DevBuf tickets, qinfo, qorder, chunk_prefix, scalars, accum;
+    DevBuf bytes, meta, terms, uterms, hashes, table, head;
+    DevBuf tickets, qinfo, qorder, chunk_prefix, accum;
     DevBuf cand_key, cand_q, qcount, gstart, gcursor, seg_a, seg_b, counters;
-    DevBuf out_start, out_n, out_id, out_score, full;
+    DevBuf out_id, out_score, full;
     HostBuf h_stage, h_small, h_out;
     uint64_t tickets_slots = 0;
     uint64_t accum_words = 0;
