@@ -807,9 +807,11 @@ __global__ __launch_bounds__(1024) void group_scan_kernel(const uint32_t *qcount
     if (tid == nt - 1) { qstart[n] = s_a[nt - 1]; out_start[n] = s_b[nt - 1]; }
 }
 
-// Candidates into their query's segment.  A wavefront's 64 candidates mostly
-// belong to one query (a wavefront emits one (query, slice) at a time), so
-// each distinct query among them takes one atomic add for all its lanes.
+// Candidates into their query's segment.  Top-k candidates come in long runs
+// of one query (a wavefront emits one (query, slice) at a time), so the first
+// few distinct queries of a wavefront's 64 candidates take one atomic add for
+// all their lanes; whatever remains (threshold hits, often one per query)
+// takes one atomic per lane, all in flight together.
 __global__ __launch_bounds__(256) void group_scatter_kernel(const uint64_t *cand_key,
                                                             const uint32_t *cand_q,
                                                             const unsigned long long *n_cand,
@@ -827,7 +829,7 @@ __global__ __launch_bounds__(256) void group_scatter_kernel(const uint64_t *cand
         const uint32_t q = valid ? cand_q[i] : 0u;
         uint64_t todo = __ballot(valid);
         uint64_t pos = 0;
-        while (todo) {
+        for (int it = 0; it < 4 && todo; ++it) {
             const uint32_t leader = (uint32_t)__builtin_ctzll(todo);
             const uint32_t ql = lane_u32(q, leader);
             const uint64_t m = __ballot(valid && q == ql) & todo;
@@ -837,6 +839,7 @@ __global__ __launch_bounds__(256) void group_scatter_kernel(const uint64_t *cand
             if ((m >> lane) & 1ull) pos = (uint64_t)qstart[ql] + b0 + __popcll(m & ((1ull << lane) - 1ull));
             todo &= ~m;
         }
+        if ((todo >> lane) & 1ull) pos = (uint64_t)qstart[q] + atomicAdd(&qcursor[q], 1u);
         if (valid) seg[pos] = cand_key[i];
     }
 }
