@@ -147,6 +147,10 @@ def lib():
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+            # torch first: the library then binds to the HIP runtime torch
+            # loaded (same soname) instead of bringing a second one into the
+            # process, which would not see the device
+            import torch  # noqa: F401
             L = C.CDLL(LIB_PATH)
             for name, (res, args) in EXPORTS.items():
                 f = getattr(L, name)

@@ -85,6 +85,7 @@ def devlib():
             if not os.path.exists(_DEVLIB):
                 raise RuntimeError("synth/libsynth_dev.so is not built "
                                    "(run __graft_entry__.build())")
+            import torch  # noqa: F401  (bind to torch's HIP runtime, not a second copy)
             L = C.CDLL(_DEVLIB)
             L.synth_dev_doc_bases.restype = C.c_int
             L.synth_dev_doc_bases.argtypes = [C.c_uint64, C.c_void_p, C.c_uint32,
