@@ -15,7 +15,7 @@ ARCH = os.environ.get("COBS_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I", os.path.join(PKG, "..", "include")]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_SOURCES = ["lib.cpp", "serve.cpp", "docset.cpp"]
+HOST_SOURCES = ["lib.cpp", "query.cpp", "index_ops.cpp", "serve.cpp", "docset.cpp"]
 DEVICE_SOURCES = ["kernels.hip"]
 
 

@@ -137,6 +137,17 @@ struct cobs_index {
 
 namespace cobs {
 
+// Shared helpers of the host runtime (lib.cpp).
+cobs_status check_params(const cobs_params *p);
+TermSpec term_spec(const cobs_params &p);
+// Index layout for the order already in ix and these block sizes: row counts,
+// strides, offsets, slices and score-buffer offsets (host only).
+cobs_status layout_blocks(cobs_index *ix, const std::vector<uint32_t> &block_docs);
+// The layout a build gives: compact order by (distinct terms, input id), blocks of B.
+cobs_status make_layout(cobs_index *ix);
+// Device copies of the order and the slice table.
+cobs_status upload_layout(cobs_index *ix, hipStream_t st);
+
 Workspace *acquire_workspace(cobs_index *ix);
 void release_workspace(cobs_index *ix, Workspace *ws);
 
