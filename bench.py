@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--serve-max", type=int, default=8000)
     ap.add_argument("--serve-streams", type=int, default=4, help="batches in flight in the server")
     ap.add_argument("--tuning", type=str, default="",
-                    help="'unroll,chunk' launch shape instead of autotuning")
+                    help="'unroll,chunk[,order]' launch shape instead of autotuning")
     ap.add_argument("--offload-gb", type=float, default=30.0,
                     help="last: move the matrix to host memory and time streamed batches "
                          "with this device budget (GB) for the staging buffers; 0 skips it")
@@ -287,9 +287,9 @@ def main():
 
     # autotune the gather launch shape on a separate query set of the same shape
     if args.tuning:
-        u, c = (int(x) for x in args.tuning.split(","))
-        ix.set_tuning(u, c)
-        tuning = {"unroll": u, "chunk": c, "gather_ms": None}
+        shape = [int(x) for x in args.tuning.split(",")] + [0]
+        ix.set_tuning(shape[0], shape[1], shape[2])
+        tuning = {"unroll": shape[0], "chunk": shape[1], "order": shape[2], "gather_ms": None}
     else:
         if w.kind == "dna":
             tq = synth.dna_queries(w, n=qs.n, first=qs.n)

@@ -407,26 +407,49 @@ cobs_status cobs_serve_replay(cobs_server *s, const uint8_t *bytes, const uint64
 /* ---- tuning --------------------------------------------------------------- */
 
 /*
+ * Order in which the gather kernel's persistent wavefronts take the work
+ * items (query chunk, column slice).  In both, chunks come in query-size
+ * order, largest first.
+ *  COBS_ORDER_QUERIES  the slices of one chunk side by side (the grid drains
+ *                      evenly over the whole batch);
+ *  COBS_ORDER_SLICES   every chunk of one slice before the next slice (the
+ *                      slice's rows stay in the last-level cache while the
+ *                      batch reads them);
+ *  COBS_ORDER_AUTO     slice-major when every slice of the index holds at
+ *                      most 128 MiB of rows, else query-major.
+ */
+typedef enum {
+    COBS_ORDER_AUTO = 0,
+    COBS_ORDER_QUERIES = 1,
+    COBS_ORDER_SLICES = 2,
+} cobs_order;
+
+/*
  * Launch shape of the gather kernel for an index: `unroll` terms whose rows
- * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4) and `chunk`,
- * the most distinct terms per work item (longer queries are split and their
+ * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4), `chunk`, the
+ * most distinct terms per work item (longer queries are split and their
  * counts merged; a batch is split into about two work items per resident
- * wavefront, with items of at most `chunk` terms).  0 = defaults (8 or 2;
- * 16384).  Results never depend on either.
+ * wavefront, with items of at most `chunk` terms), and `order` (cobs_order).
+ * 0 = defaults (8 or 2; 16384; COBS_ORDER_AUTO).  Results never depend on
+ * any of them.
  */
 typedef struct {
     uint32_t unroll;
     uint32_t chunk;
     double gather_ms;    /* cobs_tune: the chosen shape's gather time */
+    uint32_t order;
 } cobs_tuning;
 
 /* Time the gather kernel on the sample batch for every supported unroll and
- * chunk in {default, 512, 1024, 2048, 4096, 8192, 16384, 2^20}, keep the
- * fastest pair for this index, report it in *best.
+ * chunk in {default, 512, 1024, 2048, 4096, 8192, 16384, 2^20} in the
+ * index's automatic order, then the other order at the fastest pair; keep
+ * the fastest shape for this index and report it in *best (order 1 or 2).
  * The sample should resemble the batches to come (a separate query set). */
 cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
                       uint32_t n_queries, uint32_t mem, void *stream, cobs_tuning *best);
-/* Set (or, with zeros, reset) the launch shape explicitly. */
+/* Set (or, with zeros, reset) the launch shape explicitly; gather_ms is
+ * ignored.  EINVAL: an unroll the index does not support, or an order above
+ * COBS_ORDER_SLICES. */
 cobs_status cobs_set_tuning(cobs_index *ix, const cobs_tuning *t);
 
 /* ---- measurement -------------------------------------------------------- */

@@ -22,6 +22,7 @@ OK, EINVAL, ENOMEM, EBUDGET, EOVERFLOW, EDEVICE, ECANCELLED, ESTATE = range(8)
 DNA, BYTES = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 MODE_BATCHED, MODE_PLAIN = 0, 1
+ORDER_AUTO, ORDER_QUERIES, ORDER_SLICES = 0, 1, 2   # cobs_order: gather work-item order
 
 
 class CobsError(RuntimeError):
@@ -73,7 +74,8 @@ class ServeStats(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("unroll", C.c_uint32), ("chunk", C.c_uint32), ("gather_ms", C.c_double)]
+    _fields_ = [("unroll", C.c_uint32), ("chunk", C.c_uint32), ("gather_ms", C.c_double),
+                ("order", C.c_uint32)]
 
 
 class KernelTiming(C.Structure):
@@ -350,10 +352,10 @@ class Index:
         t = Tuning()
         _check(lib().cobs_tune(self._h, ptr, _p(qo), len(qo) - 1, mem, _stream(stream),
                                C.byref(t)))
-        return dict(unroll=t.unroll, chunk=t.chunk, gather_ms=t.gather_ms)
+        return dict(unroll=t.unroll, chunk=t.chunk, order=t.order, gather_ms=t.gather_ms)
 
-    def set_tuning(self, unroll=0, chunk=0) -> None:
-        t = Tuning(unroll, chunk, 0.0)
+    def set_tuning(self, unroll=0, chunk=0, order=ORDER_AUTO) -> None:
+        t = Tuning(unroll, chunk, 0.0, order)
         _check(lib().cobs_set_tuning(self._h, C.byref(t)))
 
     def query_flat(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,

@@ -88,6 +88,10 @@ struct GatherArgs {
     uint32_t *full_scores;             // optional [n_queries * n_docs]
     uint64_t cand_cap;
     uint32_t n_queries, n_slices, h, chunk, topk, n_docs;
+    // item order: 0 = query-major (the slices of one chunk side by side,
+    // chunks in qorder order); 1 = slice-major (every chunk of one slice, in
+    // qorder order, before the next slice)
+    uint32_t slice_major;
 };
 
 // ---- query path ----------------------------------------------------------

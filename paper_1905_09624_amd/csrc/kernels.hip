@@ -332,9 +332,10 @@ __global__ __launch_bounds__(1024) void dedup_global_kernel(const uint64_t *term
 
 // ---- plan ------------------------------------------------------------------------------
 
-// Work items are ordered by query size class (floor(log2 l), largest first;
-// the order within a class is arbitrary), so the last items to start are
-// the smallest and the persistent grid drains evenly.
+// Chunks are ordered by query size class (floor(log2 l), largest first;
+// the order within a class is arbitrary), so the last items to start (of
+// the launch, or of each slice in slice-major order) are the smallest and
+// the persistent grid drains evenly.
 __device__ __forceinline__ uint32_t size_class(uint32_t ell) { return __clz(ell); }   // 0..32
 
 __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, const uint64_t *wbase,
@@ -534,7 +535,10 @@ template <int P, int U, bool kH1>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 {
     const uint32_t lane = lane_id();
-    const uint64_t total = (uint64_t)a.chunk_prefix[a.n_queries] * a.n_slices;
+    const uint32_t n_chunks = a.chunk_prefix[a.n_queries];
+    const uint64_t total = (uint64_t)n_chunks * a.n_slices;
+    // item = major * minor_count + minor
+    const uint32_t minor_count = a.slice_major ? n_chunks : a.n_slices;
     Counter<P> cnt;
 
     for (;;) {
@@ -542,9 +546,12 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
         if (lane == 0) item = atomicAdd(a.work_counter, 1ull);
         item = bcast64(item);
         if (item >= total) break;
-        // items in query-size order, the slices of one chunk side by side
-        const uint32_t c = (uint32_t)(item / a.n_slices);
-        const uint32_t sl = (uint32_t)(item - (uint64_t)c * a.n_slices);
+        // chunks in query-size order; the slices of one chunk side by side,
+        // or one slice at a time (its rows then stay in the last-level cache)
+        const uint32_t major = (uint32_t)(item / minor_count);
+        const uint32_t minor = (uint32_t)(item - (uint64_t)major * minor_count);
+        const uint32_t c = a.slice_major ? minor : major;
+        const uint32_t sl = a.slice_major ? major : minor;
         const uint32_t rank = bsearch_le(a.chunk_prefix, a.n_queries, c);
         const uint32_t qi = a.qorder[rank];
         const uint32_t chunk = c - a.chunk_prefix[rank];

@@ -72,6 +72,21 @@ uint32_t auto_chunk(uint64_t W, uint32_t n_slices, int grid, uint32_t cap)
     return (uint32_t)c;
 }
 
+// Slice-major order keeps one slice's rows in the last-level cache (256 MB
+// on MI355X) while every chunk of the batch reads them; it pays where a
+// slice fits there with room to spare and the batch re-reads rows (h > 1
+// terms share rows, common text q-grams recur across queries).  Larger
+// slices are read in query-major order, whose largest-first items balance
+// the grid best.
+constexpr uint64_t kSliceMajorBytes = 128ull << 20;
+
+uint32_t default_order(const cobs_index *ix)
+{
+    uint64_t biggest = 0;
+    for (const SliceDesc &sd : ix->slices) biggest = std::max<uint64_t>(biggest, (uint64_t)sd.rows * sd.width);
+    return biggest <= kSliceMajorBytes ? COBS_ORDER_SLICES : COBS_ORDER_QUERIES;
+}
+
 }  // namespace
 
 // The gather of an offloaded index: group by group, the copy of group g + 2
@@ -319,6 +334,8 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         ga.chunk = C;
         ga.topk = b.topk;
         ga.n_docs = ix->n_docs;
+        const uint32_t order = b.order ? b.order : (ix->tuned_order ? ix->tuned_order : default_order(ix));
+        ga.slice_major = order == COBS_ORDER_SLICES ? 1u : 0u;
         const bool prof = g_prof.load() != 0;
         const bool timed = prof || b.time_gather;
         if (timed) {
@@ -640,8 +657,10 @@ cobs_status cobs_set_tuning(cobs_index *ix, const cobs_tuning *t)
     if (!ix || !t) return set_error(COBS_EINVAL, "NULL argument");
     if (t->unroll && !gather_unroll_valid((int)t->unroll, (int)ix->prm.num_hashes))
         return set_error(COBS_EINVAL, "unsupported unroll for this index");
+    if (t->order > COBS_ORDER_SLICES) return set_error(COBS_EINVAL, "unknown work-item order");
     ix->tuned_unroll = (int)t->unroll;
     ix->tuned_chunk = t->chunk;
+    ix->tuned_order = t->order;
     return COBS_OK;
 }
 
@@ -653,34 +672,49 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
     const int unrolls[2] = {h == 1 ? 4 : 2, h == 1 ? 8 : 4};
     const uint32_t chunks[] = {0, 512, 1024, 2048, 4096, 8192, 16384, 1u << 20};
     Workspace *ws = acquire_workspace(ix);
-    cobs_tuning win{0, 0, 1e300};
+    const uint32_t order0 = default_order(ix);
+    cobs_tuning win{0, 0, 1e300, order0};
     cobs_status s = COBS_OK;
+    auto time_shape = [&](int u, uint32_t c, uint32_t order) -> double {
+        BatchSpec spec;
+        spec.bytes = bytes;
+        spec.q_off = q_off;
+        spec.n = n_queries;
+        spec.mem = mem;
+        spec.k_num = 1;
+        spec.k_den = 1;
+        spec.unroll = (uint32_t)u;
+        spec.chunk_cap = c;
+        spec.order = order;
+        spec.time_gather = true;
+        double t = 1e300;
+        for (int rep = 0; rep < 2 && s == COBS_OK; ++rep) {   // first run warms up
+            BatchOut bo;
+            s = run_batch(ix, *ws, spec, (hipStream_t)stream, bo);
+            if (rep) t = bo.gather_ms;
+        }
+        return t;
+    };
+    // every (unroll, chunk) in the index's default order, then the other
+    // order at the winning shape
     for (int u : unrolls) {
         for (uint32_t c : chunks) {
-            BatchSpec spec;
-            spec.bytes = bytes;
-            spec.q_off = q_off;
-            spec.n = n_queries;
-            spec.mem = mem;
-            spec.k_num = 1;
-            spec.k_den = 1;
-            spec.unroll = (uint32_t)u;
-            spec.chunk_cap = c;
-            spec.time_gather = true;
-            double t = 1e300;
-            for (int rep = 0; rep < 2 && s == COBS_OK; ++rep) {   // first run warms up
-                BatchOut bo;
-                s = run_batch(ix, *ws, spec, (hipStream_t)stream, bo);
-                if (rep) t = bo.gather_ms;
-            }
+            const double t = time_shape(u, c, order0);
             if (s != COBS_OK) break;
-            if (t < win.gather_ms) win = cobs_tuning{(uint32_t)u, c, t};
+            if (t < win.gather_ms) win = cobs_tuning{(uint32_t)u, c, t, order0};
         }
+        if (s != COBS_OK) break;
+    }
+    if (s == COBS_OK) {
+        const uint32_t other = order0 == COBS_ORDER_SLICES ? COBS_ORDER_QUERIES : COBS_ORDER_SLICES;
+        const double t = time_shape((int)win.unroll, win.chunk, other);
+        if (s == COBS_OK && t < win.gather_ms) win = cobs_tuning{win.unroll, win.chunk, t, other};
     }
     release_workspace(ix, ws);
     if (s != COBS_OK) return s;
     ix->tuned_unroll = (int)win.unroll;
     ix->tuned_chunk = win.chunk;
+    ix->tuned_order = win.order;
     *best = win;
     return COBS_OK;
 }

@@ -87,6 +87,7 @@ struct BatchSpec {
     uint32_t chunk = 0;                // terms per work item; 0 = automatic
     uint32_t chunk_cap = 0;            // automatic chunk's maximum; 0 = tuned or kDefaultChunkCap
     uint32_t unroll = 0;               // terms in flight per wavefront; 0 = tuned or default
+    uint32_t order = 0;                // cobs_order of the work items; 0 = tuned or by slice size
     uint32_t *full_scores = nullptr;   // host [n * n_docs]: full score mode
     uint64_t *terms_out = nullptr;     // host [windows]: terms-only mode
     const uint32_t *slots = nullptr;   // host [n]: score-buffer slot of each query in accum
@@ -111,6 +112,7 @@ struct cobs_index {
     cobs::Seeds seeds{};
     int tuned_unroll = 0;              // set by cobs_tune (0 = default)
     uint32_t tuned_chunk = 0;          // set by cobs_tune (0 = automatic)
+    uint32_t tuned_order = 0;          // set by cobs_tune (0 = by slice size)
     uint64_t acc_words = 0;            // words of one query's score buffer
     std::mutex pool_mu;
     std::vector<cobs::Workspace *> pool;

@@ -54,6 +54,12 @@ def test_offloaded_results_equal_device_resident(built):
         assert np.array_equal(ix.read(0, info["total_bytes"]), matrix)
         _same(_results(ix, qs), before)
         _same(_results(ix, qs), before)   # staging buffers reused across batches
+        for order in (cobs.ORDER_QUERIES, cobs.ORDER_SLICES):   # within each group
+            ix.set_tuning(0, 0, order)
+            try:
+                _same(_results(ix, qs), before)
+            finally:
+                ix.set_tuning(0, 0)
         srv = cobs.Server(ix, num_streams=3)
         tickets = [srv.submit(qs.get(i), k=(1, 2)) for i in range(qs.n)]
         served = [srv.wait(t) for t in tickets]

@@ -304,31 +304,33 @@ def test_very_long_queries_use_wide_counters():
         assert np.array_equal(hits[i][0], ids) and np.array_equal(hits[i][1], scores), i
 
 
-@pytest.mark.parametrize("unroll,chunk", [(4, 32), (8, 100), (4, 1024), (8, 7), (8, 1 << 20)])
-def test_launch_shapes_give_identical_results(workload, unroll, chunk):
-    # every instantiated unroll and several term-chunk sizes (many merges at
-    # chunk 7, every query in one work item at 2^20) give the oracle's scores
-    # (K = 0 reports every document with its score) and hits
+@pytest.mark.parametrize("unroll,chunk,order", [(4, 32, 1), (8, 100, 2), (4, 1024, 1), (8, 7, 1),
+                                                (8, 7, 2), (8, 1 << 20, 1), (4, 1 << 20, 2)])
+def test_launch_shapes_give_identical_results(workload, unroll, chunk, order):
+    # every instantiated unroll, both work-item orders (query-major 1,
+    # slice-major 2) and several term-chunk sizes (many merges at chunk 7,
+    # every query in one work item at 2^20) give the oracle's scores (K = 0
+    # reports every document with its score) and hits
     w, d, qs, gix, oix = workload
     if w.h > 1:
         unroll //= 2
-    gix.set_tuning(unroll, 0)
+    gix.set_tuning(unroll, 0, order)
     try:
         res = gix.query(qs.bytes, qs.q_off, k=(0, 1), chunk=chunk)
         for i in range(qs.n):
             want, wl = oix.query_scores(qs.get(i))
             ids, sc, l = res[i]
-            assert l == wl, (unroll, chunk, i)
+            assert l == wl, (unroll, chunk, order, i)
             full = np.zeros_like(want)
             full[ids] = sc
             assert len(ids) == (len(want) if wl else 0)
             if wl:
-                assert np.array_equal(full, want), (unroll, chunk, i)
+                assert np.array_equal(full, want), (unroll, chunk, order, i)
         res = gix.query(qs.bytes, qs.q_off, k=(1, 2), topk=4, chunk=chunk)
         for i in range(qs.n):
             ids, sc, l = oix.query(qs.get(i), 1, 2, 4)
-            assert res[i][2] == l and np.array_equal(res[i][0], ids), (unroll, chunk, i)
-            assert np.array_equal(res[i][1], sc), (unroll, chunk, i)
+            assert res[i][2] == l and np.array_equal(res[i][0], ids), (unroll, chunk, order, i)
+            assert np.array_equal(res[i][1], sc), (unroll, chunk, order, i)
     finally:
         gix.set_tuning(0, 0)
 
@@ -347,11 +349,20 @@ def test_tuned_chunk_caps_the_split(workload):
             assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
 
 
+def test_set_tuning_refuses_unknown_order(workload):
+    cobs = _cobs()
+    w, d, qs, gix, oix = workload
+    with pytest.raises(cobs.CobsError) as e:
+        gix.set_tuning(0, 0, 3)
+    assert e.value.status == cobs.EINVAL
+
+
 def test_autotune_keeps_results(workload):
     w, d, qs, gix, oix = workload
     before = gix.query(qs.bytes, qs.q_off, k=(1, 2))
     t = gix.tune(qs.bytes, qs.q_off)
     assert t["gather_ms"] > 0 and t["unroll"] in ((4, 8) if w.h == 1 else (2, 4))
+    assert t["order"] in (_cobs().ORDER_QUERIES, _cobs().ORDER_SLICES)
     after = gix.query(qs.bytes, qs.q_off, k=(1, 2))
     for x, y in zip(before, after):
         assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
