@@ -330,6 +330,25 @@ cobs_status cobs_query_results(cobs_index *ix, const uint8_t *bytes, const uint6
                                uint32_t n_queries, const cobs_query_opts *opts, void *stream,
                                cobs_results **out);
 /*
+ * Query several indexes as one collection (the paper's tool queries several
+ * index files, so that a front-end can pick datasets or categories: section
+ * 6).  Documents are numbered across the indexes in the given order: input
+ * document d of indexes[j] is n_docs(0) + ... + n_docs(j - 1) + d.  The
+ * indexes must share the term definition (kind, q, canonical), so each
+ * query has the same l, and the same threshold T, in every one; h, p, seed
+ * and block size may differ.  Every index runs the batch (opts as in
+ * cobs_query_batch) on `stream` in turn; each query's hits over all of them
+ * are ordered by (score desc, global id asc), and top-k keeps the topk best
+ * over the union.  The result is the query of the compact merge of the
+ * indexes (cobs_index_merge), without building it.
+ * Errors: EINVAL (NULL or no index, differing kind/q/canonical or device,
+ * more than 2^32 - 1 documents in all), and those of cobs_query_batch.
+ */
+cobs_status cobs_query_multi(cobs_index *const *indexes, uint32_t n_indexes,
+                             const uint8_t *bytes, const uint64_t *q_off, uint32_t n_queries,
+                             const cobs_query_opts *opts, void *stream, cobs_results **out);
+
+/*
  * View of a result object: query i's hits are doc_id[hit_off[i] .. hit_off[i+1])
  * with score[] alongside, ordered by (score desc, input id asc); num_terms[i]
  * is l.  Pointers stay valid until cobs_results_free.

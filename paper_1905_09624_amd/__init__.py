@@ -123,6 +123,9 @@ EXPORTS = {
                                     C.POINTER(C.POINTER(C.c_uint32)),
                                     C.POINTER(C.POINTER(C.c_uint32))]),
     "cobs_results_free": (None, [C.c_void_p]),
+    "cobs_query_multi": (C.c_int, [C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p, C.c_void_p,
+                                   C.c_uint32, C.POINTER(QueryOpts), C.c_void_p,
+                                   C.POINTER(C.c_void_p)]),
     "cobs_serve": (C.c_int, [C.c_void_p, C.POINTER(ServeOpts), C.POINTER(C.c_void_p)]),
     "cobs_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
                               C.c_uint32, C.c_uint64, C.POINTER(C.c_uint64)]),
@@ -370,24 +373,7 @@ class Index:
         r = C.c_void_p()
         _check(lib().cobs_query_results(self._h, ptr, _p(qo), n, C.byref(opts), _stream(stream),
                                         C.byref(r)))
-        try:
-            nq = C.c_uint32()
-            nt, off, ids, sc = (C.POINTER(C.c_uint32)(), C.POINTER(C.c_uint64)(),
-                                C.POINTER(C.c_uint32)(), C.POINTER(C.c_uint32)())
-            _check(lib().cobs_results_view(r, C.byref(nq), C.byref(nt), C.byref(off),
-                                           C.byref(ids), C.byref(sc)))
-            num_terms = np.ctypeslib.as_array(nt, (n,)).copy() if n else np.zeros(0, np.uint32)
-            hit_off = np.ctypeslib.as_array(off, (n + 1,)).copy()
-            total = int(hit_off[-1])
-            if total:
-                doc_ids = np.ctypeslib.as_array(ids, (total,)).copy()
-                scores = np.ctypeslib.as_array(sc, (total,)).copy()
-            else:
-                doc_ids = np.zeros(0, np.uint32)
-                scores = np.zeros(0, np.uint32)
-            return num_terms, hit_off, doc_ids, scores
-        finally:
-            lib().cobs_results_free(r)
+        return _take_results(r, n)
 
     def query(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
               stream=None, chunk=0):
@@ -492,6 +478,45 @@ class Server:
         _check(lib().cobs_serve_stop(self._h, C.byref(st)))
         self._h = None
         return {f: getattr(st, f) for f, _ in ServeStats._fields_}
+
+
+def _take_results(r, n):
+    """Copy a cobs_results object into numpy arrays and free it."""
+    try:
+        nq = C.c_uint32()
+        nt, off, ids, sc = (C.POINTER(C.c_uint32)(), C.POINTER(C.c_uint64)(),
+                            C.POINTER(C.c_uint32)(), C.POINTER(C.c_uint32)())
+        _check(lib().cobs_results_view(r, C.byref(nq), C.byref(nt), C.byref(off),
+                                       C.byref(ids), C.byref(sc)))
+        num_terms = np.ctypeslib.as_array(nt, (n,)).copy() if n else np.zeros(0, np.uint32)
+        hit_off = np.ctypeslib.as_array(off, (n + 1,)).copy()
+        total = int(hit_off[-1])
+        if total:
+            doc_ids = np.ctypeslib.as_array(ids, (total,)).copy()
+            scores = np.ctypeslib.as_array(sc, (total,)).copy()
+        else:
+            doc_ids = np.zeros(0, np.uint32)
+            scores = np.zeros(0, np.uint32)
+        return num_terms, hit_off, doc_ids, scores
+    finally:
+        lib().cobs_results_free(r)
+
+
+def query_multi(indexes, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
+                stream=None, chunk=0):
+    """Query several indexes as one collection (cobs_query_multi): list of
+    (doc_ids, scores, num_terms) per query, ids numbered across the indexes
+    in order."""
+    ptr, mem, keep = _byte_source(data)
+    qo = np.ascontiguousarray(q_off, dtype=np.uint64)
+    n = len(qo) - 1
+    opts = QueryOpts(k[0], k[1], topk, score_bits, mode, mem, chunk)
+    hs = (C.c_void_p * max(len(indexes), 1))(*[ix._h for ix in indexes])
+    r = C.c_void_p()
+    _check(lib().cobs_query_multi(hs, len(indexes), ptr, _p(qo), n, C.byref(opts),
+                                  _stream(stream), C.byref(r)))
+    nt, off, ids, sc = _take_results(r, n)
+    return [(ids[off[i]:off[i + 1]], sc[off[i]:off[i + 1]], int(nt[i])) for i in range(n)]
 
 
 def now_ns() -> int:

@@ -598,6 +598,72 @@ cobs_status cobs_query_results(cobs_index *ix, const uint8_t *bytes, const uint6
     return COBS_OK;
 }
 
+cobs_status cobs_query_multi(cobs_index *const *ixs, uint32_t n_indexes, const uint8_t *bytes,
+                             const uint64_t *q_off, uint32_t n_queries,
+                             const cobs_query_opts *opts, void *stream, cobs_results **out)
+{
+    if (!ixs || !opts || !out || n_indexes == 0) return set_error(COBS_EINVAL, "NULL argument");
+    *out = nullptr;
+    for (uint32_t j = 0; j < n_indexes; ++j)
+        if (!ixs[j]) return set_error(COBS_EINVAL, "NULL index");
+    const cobs_params &p0 = ixs[0]->prm;
+    uint64_t total_docs = 0;
+    std::vector<uint32_t> base(n_indexes);
+    for (uint32_t j = 0; j < n_indexes; ++j) {
+        const cobs_index *ix = ixs[j];
+        if (ix->prm.kind != p0.kind || ix->prm.q != p0.q || ix->prm.canonical != p0.canonical)
+            return set_error(COBS_EINVAL, "indexes must share kind, q and canonical");
+        if (ix->device != ixs[0]->device) return set_error(COBS_EINVAL, "indexes on different devices");
+        base[j] = (uint32_t)total_docs;
+        total_docs += ix->n_docs;
+    }
+    if (total_docs > 0xFFFFFFFFull) return set_error(COBS_EINVAL, "more than 2^32 - 1 documents");
+    // every index's hits, per query, in (score desc, local id asc) order
+    std::vector<cobs_results> part(n_indexes);
+    for (uint32_t j = 0; j < n_indexes; ++j) {
+        cobs_results &r = part[j];
+        r.num_terms.assign(n_queries, 0);
+        r.off.assign((size_t)n_queries + 1, 0);
+        cobs_status s = query_driver(ixs[j], bytes, q_off, n_queries, opts, stream,
+                                     [&](const BatchOut &bo, uint32_t q0, uint32_t n) {
+                                         const uint64_t b = r.ids.size(), tot = bo.start[n];
+                                         r.ids.insert(r.ids.end(), bo.ids, bo.ids + tot);
+                                         r.scores.insert(r.scores.end(), bo.scores, bo.scores + tot);
+                                         for (uint32_t i = 0; i < n; ++i) {
+                                             r.num_terms[q0 + i] = bo.num_terms[i];
+                                             r.off[q0 + i + 1] = b + bo.start[i + 1];
+                                         }
+                                         return COBS_OK;
+                                     });
+        if (s != COBS_OK) return s;
+        if (j && r.num_terms != part[0].num_terms)
+            return set_error(COBS_EDEVICE, "indexes disagree on a query's distinct terms");
+    }
+    // merge: equal scores come in index order, then local id order, which is
+    // global id order because the bases increase with the index
+    auto *res = new cobs_results();
+    res->num_terms = part[0].num_terms;
+    res->off.assign((size_t)n_queries + 1, 0);
+    std::vector<std::pair<uint32_t, uint32_t>> hits;   // (score, global id)
+    for (uint32_t i = 0; i < n_queries; ++i) {
+        hits.clear();
+        for (uint32_t j = 0; j < n_indexes; ++j)
+            for (uint64_t x = part[j].off[i]; x < part[j].off[i + 1]; ++x)
+                hits.emplace_back(part[j].scores[x], base[j] + part[j].ids[x]);
+        std::stable_sort(hits.begin(), hits.end(),
+                         [](const auto &a, const auto &b) { return a.first > b.first; });
+        size_t keep = hits.size();
+        if (opts->topk && keep > opts->topk) keep = opts->topk;
+        for (size_t x = 0; x < keep; ++x) {
+            res->ids.push_back(hits[x].second);
+            res->scores.push_back(hits[x].first);
+        }
+        res->off[i + 1] = res->ids.size();
+    }
+    *out = res;
+    return COBS_OK;
+}
+
 cobs_status cobs_results_view(const cobs_results *r, uint32_t *n_queries,
                               const uint32_t **num_terms, const uint64_t **hit_off,
                               const uint32_t **doc_id, const uint32_t **score)
