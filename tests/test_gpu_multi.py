@@ -91,6 +91,7 @@ def test_multi_of_one_index_is_the_index(parts):
     cobs, rng, docs, built = parts
     qs, data, off = _queries(rng, docs)
     ix = built[1][0]
+    assert cobs.query_multi([ix, built[0][0]], b"", np.zeros(1, np.uint64)) == []   # no queries
     for k, topk in (((1, 2), 0), ((0, 1), 3)):
         for x, y in zip(cobs.query_multi([ix], data, off, k=k, topk=topk),
                         ix.query(data, off, k=k, topk=topk)):
