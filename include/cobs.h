@@ -27,6 +27,11 @@
  *    memory); later calls must run on the same device.
  *  - Scores are integers; nothing on the path uses floating point except the
  *    one-time filter sizing on the host.
+ *  - Threads: query calls on one index may run at once from several threads
+ *    (each takes a workspace of its own from the index's pool).  Calls that
+ *    change an index (cobs_tune, cobs_set_tuning, cobs_index_offload,
+ *    cobs_index_onload, cobs_index_free) must not overlap any other call on
+ *    that index, a running server's included.
  */
 #ifndef COBS_H
 #define COBS_H
