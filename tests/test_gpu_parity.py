@@ -349,6 +349,36 @@ def test_tuned_chunk_caps_the_split(workload):
             assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
 
 
+def test_concurrent_queries_from_threads(workload):
+    # query calls on one index from several threads at once, each on its own
+    # stream (each call takes its own workspace), give the single-thread hits
+    import threading
+    import torch
+    w, d, qs, gix, oix = workload
+    want = [gix.query(qs.bytes, qs.q_off, k=(1, 2)), gix.query(qs.bytes, qs.q_off, k=(0, 1), topk=3)]
+    errors = []
+
+    def worker(t):
+        try:
+            st = torch.cuda.Stream()
+            for rep in range(4):
+                j = (t + rep) % 2
+                got = gix.query(qs.bytes, qs.q_off, k=((1, 2), (0, 1))[j], topk=(0, 3)[j], stream=st)
+                for x, y in zip(got, want[j]):
+                    if not (np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) and x[2] == y[2]):
+                        errors.append((t, rep))
+                        return
+        except Exception as e:   # reported below
+            errors.append((t, repr(e)))
+
+    ths = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    assert not errors, errors
+
+
 def test_set_tuning_refuses_unknown_order(workload):
     cobs = _cobs()
     w, d, qs, gix, oix = workload
