@@ -476,6 +476,36 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
  * COBS_ORDER_SLICES. */
 cobs_status cobs_set_tuning(cobs_index *ix, const cobs_tuning *t);
 
+/* ---- device memory ------------------------------------------------------ */
+
+/*
+ * Where the library's device memory comes from.  By default every device
+ * allocation (matrices, order and slice tables, query workspaces, server
+ * score pools, out-of-core staging buffers) is a hipMalloc and is released
+ * with hipFree.  A caller that manages device memory itself, such as a
+ * framework's caching allocator, installs its own pair here:
+ *  alloc(ctx, bytes)  device memory of the current device, at least
+ *                     256-byte aligned, or NULL when it cannot (the library
+ *                     call then fails with ENOMEM);
+ *  free(ctx, ptr)     gives back a pointer alloc returned.  The library waits
+ *                     for the device to be idle before it calls free, so
+ *                     the memory may be handed out again at once.
+ * Both may be called from any thread, server workers included, and must not
+ * call into this library.  Every allocation is released through the pair
+ * that made it, so the pair and its ctx must stay valid until the last
+ * object holding such memory is freed.  Installing a pair affects later
+ * allocations only; NULL (or alloc == NULL) restores hipMalloc/hipFree.
+ * Pinned host memory (hipHostMalloc) is not routed.
+ * Errors: EINVAL when alloc is set and free is not.
+ */
+typedef struct {
+    void *(*alloc)(void *ctx, uint64_t bytes);
+    void (*free)(void *ctx, void *ptr);
+    void *ctx;
+} cobs_allocator;
+
+cobs_status cobs_set_allocator(const cobs_allocator *allocator);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /*

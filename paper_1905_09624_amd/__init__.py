@@ -78,6 +78,14 @@ class Tuning(C.Structure):
                 ("order", C.c_uint32)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_uint64)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
 class KernelTiming(C.Structure):
     _fields_ = [("launches", C.c_uint64), ("total_ms", C.c_double), ("last_ms", C.c_double),
                 ("row_bytes", C.c_uint64), ("terms", C.c_uint64)]
@@ -123,6 +131,7 @@ EXPORTS = {
                                     C.POINTER(C.POINTER(C.c_uint32)),
                                     C.POINTER(C.POINTER(C.c_uint32))]),
     "cobs_results_free": (None, [C.c_void_p]),
+    "cobs_set_allocator": (C.c_int, [C.POINTER(Allocator)]),
     "cobs_query_multi": (C.c_int, [C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p, C.c_void_p,
                                    C.c_uint32, C.POINTER(QueryOpts), C.c_void_p,
                                    C.POINTER(C.c_void_p)]),
@@ -517,6 +526,44 @@ def query_multi(indexes, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE
                                   _stream(stream), C.byref(r)))
     nt, off, ids, sc = _take_results(r, n)
     return [(ids[off[i]:off[i + 1]], sc[off[i]:off[i + 1]], int(nt[i])) for i in range(n)]
+
+
+# every allocator pair ever installed: memory it handed out is given back
+# through it, possibly long after another pair replaced it
+_ALLOCATORS = []
+
+
+def set_allocator(alloc=None, free=None) -> None:
+    """Route the library's device allocations through alloc(bytes) -> int
+    pointer (0 on failure) and free(pointer) (cobs_set_allocator); with no
+    arguments, back to hipMalloc/hipFree."""
+    if alloc is None:
+        _check(lib().cobs_set_allocator(None))
+        return
+
+    def _a(ctx, n):
+        try:
+            return int(alloc(int(n))) or None
+        except Exception:
+            return None
+
+    def _f(ctx, ptr):
+        free(int(ptr))
+
+    pair = Allocator(_ALLOC_FN(_a), _FREE_FN(_f), None)
+    _ALLOCATORS.append(pair)
+    _check(lib().cobs_set_allocator(C.byref(pair)))
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Take the library's device memory from torch's caching allocator (so
+    that torch and the library share one pool), or give that up."""
+    if not enable:
+        set_allocator()
+        return
+    import torch
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n),
+                  lambda ptr: torch.cuda.caching_allocator_delete(ptr))
 
 
 def now_ns() -> int:

@@ -52,12 +52,12 @@ cobs_status setup_staging(cobs_index *ix, const std::vector<cobs_index::Group> &
     for (const auto &gr : groups)
         for (uint32_t i = 0; i < gr.n_slices; ++i) rebased[gr.slice0 + i].base -= gr.off;
     for (int i = 0; i < 2; ++i) {
-        if (stage) COBS_HIP(hipMalloc(&ix->d_stage[i], stage));
+        if (stage) COBS_HIP(dev_alloc(&ix->d_stage[i], stage));
         COBS_HIP(hipEventCreateWithFlags(&ix->ev_copy[i], hipEventDisableTiming));
         COBS_HIP(hipEventCreateWithFlags(&ix->ev_done[i], hipEventDisableTiming));
     }
     COBS_HIP(hipStreamCreateWithFlags(&ix->copy_stream, hipStreamNonBlocking));
-    COBS_HIP(hipMalloc(&ix->d_group_slices, std::max<size_t>(rebased.size(), 1) * sizeof(SliceDesc)));
+    COBS_HIP(dev_alloc(&ix->d_group_slices, std::max<size_t>(rebased.size(), 1) * sizeof(SliceDesc)));
     if (!rebased.empty())
         COBS_HIP(hipMemcpy(ix->d_group_slices, rebased.data(), rebased.size() * sizeof(SliceDesc),
                            hipMemcpyHostToDevice));
@@ -92,7 +92,7 @@ cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes)
         ix->release_offload();
         return s;
     }
-    if (ix->d_matrix) (void)hipFree(ix->d_matrix);
+    dev_free(ix->d_matrix);
     ix->d_matrix = nullptr;
     return COBS_OK;
 }
@@ -263,11 +263,8 @@ cobs_status cobs_index_load(const char *path, int device, uint64_t device_budget
         if ((s = setup_staging(ix.get(), groups, stage)) != COBS_OK) return s;
     } else {
         if (T) {
-            hipError_t e = hipMalloc(&ix->d_matrix, T);
-            if (e != hipSuccess) {
-                ix->d_matrix = nullptr;
+            if (dev_alloc(&ix->d_matrix, T) != hipSuccess)
                 return set_error(COBS_ENOMEM, "device memory for the matrix");
-            }
             HostBuf stage;
             COBS_HIP(stage.ensure(std::min(kFileChunk, T)));
             for (uint64_t o = 0; o < T; o += kFileChunk) {
@@ -319,11 +316,8 @@ cobs_status cobs_index_merge(const cobs_index *a, const cobs_index *b, cobs_inde
     if (s != COBS_OK) return s;
     hipStream_t st = nullptr;
     if (ix->total_bytes) {
-        hipError_t e = hipMalloc(&ix->d_matrix, ix->total_bytes);
-        if (e != hipSuccess) {
-            ix->d_matrix = nullptr;
+        if (dev_alloc(&ix->d_matrix, ix->total_bytes) != hipSuccess)
             return set_error(COBS_ENOMEM, "device memory for the matrix");
-        }
     }
     if (classic && ix->n_docs) {
         const Block &o = ix->blocks[0];
@@ -360,10 +354,10 @@ cobs_status cobs_index_onload(cobs_index *ix)
     if (!ix->h_matrix) return set_error(COBS_ESTATE, "the matrix is already in device memory");
     (void)hipSetDevice(ix->device);
     uint8_t *d = nullptr;
-    hipError_t e = hipMalloc(&d, std::max<uint64_t>(ix->total_bytes, 1));
+    hipError_t e = dev_alloc(&d, std::max<uint64_t>(ix->total_bytes, 1));
     if (e != hipSuccess) return set_error(COBS_ENOMEM, "device memory for the matrix");
     if (ix->total_bytes && (e = hipMemcpy(d, ix->h_matrix, ix->total_bytes, hipMemcpyHostToDevice)) != hipSuccess) {
-        (void)hipFree(d);
+        dev_free(d);
         return hip_error(e, "hipMemcpy(matrix to device)");
     }
     ix->d_matrix = d;

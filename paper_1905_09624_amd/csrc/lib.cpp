@@ -47,9 +47,61 @@ uint64_t now_ns()
     return (uint64_t)t.tv_sec * 1000000000ull + (uint64_t)t.tv_nsec;
 }
 
+namespace {
+
+std::mutex g_alloc_mu;
+cobs_allocator g_alloc{};                                  // alloc == NULL: hipMalloc
+std::unordered_map<void *, cobs_allocator> g_alloc_owner;   // caller-allocated pointers
+
+}  // namespace
+
+hipError_t dev_alloc(void **p, size_t bytes)
+{
+    cobs_allocator a;
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        a = g_alloc;
+    }
+    if (!a.alloc) {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) *p = nullptr;
+        return e;
+    }
+    void *q = a.alloc(a.ctx, bytes);
+    *p = q;
+    if (!q) return hipErrorOutOfMemory;
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_alloc_owner[q] = a;
+    return hipSuccess;
+}
+
+void dev_free(void *p)
+{
+    if (!p) return;
+    cobs_allocator a{};
+    bool owned = false;
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        auto it = g_alloc_owner.find(p);
+        if (it != g_alloc_owner.end()) {
+            a = it->second;
+            owned = true;
+            g_alloc_owner.erase(it);
+        }
+    }
+    if (!owned) {
+        (void)hipFree(p);
+        return;
+    }
+    // hipFree waits for the device; a caller's allocator may hand the memory
+    // out again at once, so wait here for the work that still reads it
+    (void)hipDeviceSynchronize();
+    a.free(a.ctx, p);
+}
+
 void DevBuf::release()
 {
-    if (p) (void)hipFree(p);
+    dev_free(p);
     p = nullptr;
     cap = 0;
 }
@@ -60,11 +112,8 @@ hipError_t DevBuf::ensure(size_t bytes, bool zero, hipStream_t st)
     release();
     size_t want = bytes < 256 ? 256 : bytes + bytes / 4;
     want = (want + 255) & ~size_t(255);
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-        p = nullptr;
-        return e;
-    }
+    hipError_t e = dev_alloc(&p, want);
+    if (e != hipSuccess) return e;
     cap = want;
     if (zero) return hipMemsetAsync(p, 0, want, st);
     return hipSuccess;
@@ -154,14 +203,14 @@ using namespace cobs;
 void cobs_index::release_offload()
 {
     for (int i = 0; i < 2; ++i) {
-        if (d_stage[i]) (void)hipFree(d_stage[i]);
+        dev_free(d_stage[i]);
         if (ev_copy[i]) (void)hipEventDestroy(ev_copy[i]);
         if (ev_done[i]) (void)hipEventDestroy(ev_done[i]);
         d_stage[i] = nullptr;
         ev_copy[i] = ev_done[i] = nullptr;
     }
     if (copy_stream) (void)hipStreamDestroy(copy_stream);
-    if (d_group_slices) (void)hipFree(d_group_slices);
+    dev_free(d_group_slices);
     if (h_matrix) (void)hipHostFree(h_matrix);
     copy_stream = nullptr;
     d_group_slices = nullptr;
@@ -174,9 +223,9 @@ cobs_index::~cobs_index()
 {
     for (Workspace *w : pool) delete w;
     release_offload();
-    if (d_matrix) (void)hipFree(d_matrix);
-    if (d_order) (void)hipFree(d_order);
-    if (d_slices) (void)hipFree(d_slices);
+    dev_free(d_matrix);
+    dev_free(d_order);
+    dev_free(d_slices);
 }
 
 // ---- construction -------------------------------------------------------------
@@ -296,6 +345,18 @@ cobs_status stage_piece(cobs_builder *b, const cobs_docs *run, const Piece &pc, 
 }
 
 }  // namespace
+
+extern "C" {
+
+cobs_status cobs_set_allocator(const cobs_allocator *a)
+{
+    if (a && a->alloc && !a->free) return set_error(COBS_EINVAL, "an allocator needs a free function");
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_alloc = (a && a->alloc) ? *a : cobs_allocator{};
+    return COBS_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 
@@ -450,9 +511,9 @@ cobs_status make_layout(cobs_index *ix)
 cobs_status upload_layout(cobs_index *ix, hipStream_t st)
 {
     const uint32_t n = ix->n_docs;
-    COBS_HIP(hipMalloc(&ix->d_order, std::max<size_t>(n, 1) * 4));
+    COBS_HIP(dev_alloc(&ix->d_order, std::max<size_t>(n, 1) * 4));
     if (n) COBS_HIP(hipMemcpyAsync(ix->d_order, ix->order.data(), n * 4, hipMemcpyHostToDevice, st));
-    COBS_HIP(hipMalloc(&ix->d_slices, std::max<size_t>(ix->slices.size(), 1) * sizeof(SliceDesc)));
+    COBS_HIP(dev_alloc(&ix->d_slices, std::max<size_t>(ix->slices.size(), 1) * sizeof(SliceDesc)));
     if (!ix->slices.empty())
         COBS_HIP(hipMemcpyAsync(ix->d_slices, ix->slices.data(), ix->slices.size() * sizeof(SliceDesc),
                                 hipMemcpyHostToDevice, st));
@@ -482,8 +543,8 @@ cobs_status cobs_builder_plan(cobs_builder *b)
     b->ix = ix;
     const uint64_t off = ix->total_bytes;
     if (off) {
-        hipError_t e = hipMalloc(&ix->d_matrix, off);
-        if (e != hipSuccess) { ix->d_matrix = nullptr; return hip_error(e, "hipMalloc(matrix)"); }
+        hipError_t e = dev_alloc(&ix->d_matrix, off);
+        if (e != hipSuccess) return hip_error(e, "device memory for the matrix");
         COBS_HIP(hipMemsetAsync(ix->d_matrix, 0, off, b->st));
     }
     s = upload_layout(ix, b->st);

@@ -24,6 +24,15 @@ cobs_status hip_error(hipError_t e, const char *what);
     } while (0)
 
 // grow-only device buffer
+// Device memory of the library: hipMalloc/hipFree, or the allocator the
+// caller installed with cobs_set_allocator when the memory was allocated.
+hipError_t dev_alloc(void **p, size_t bytes);
+void dev_free(void *p);
+template <typename T> hipError_t dev_alloc(T **p, size_t bytes)
+{
+    return dev_alloc(reinterpret_cast<void **>(p), bytes);
+}
+
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;

@@ -47,6 +47,14 @@ def test_binding_covers_abi(built_lib):
     cobs.lib()
 
 
+def test_allocator_needs_a_free_function(built_lib):
+    # host-side argument check of cobs_set_allocator (no device memory touched)
+    import paper_1905_09624_amd as cobs
+    lonely = cobs.Allocator(cobs._ALLOC_FN(lambda ctx, n: None), cobs._FREE_FN(), None)
+    assert cobs.lib().cobs_set_allocator(ctypes.byref(lonely)) == cobs.EINVAL
+    assert cobs.lib().cobs_set_allocator(None) == cobs.OK
+
+
 def test_library_does_not_link_the_oracle(built_lib):
     out = subprocess.check_output(["nm", "-D", built_lib]).decode()
     assert "orc_" not in out
