@@ -188,7 +188,7 @@ def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, pl
     return out
 
 
-def cpu_baseline(w, synth, oracle, qs, budget_s):
+def cpu_baseline(w, synth, oracle, qs, budget_s, threads=None):
     """The CPU oracle on bounded samples: the S smallest documents of the
     workload (their own compact plan), for S = 32 and 256, queried with the
     query set (cycled) for half the budget each.  The time per lookup is
@@ -199,7 +199,8 @@ def cpu_baseline(w, synth, oracle, qs, budget_s):
     if w.kind != "dna" or w.n_docs < 256:
         return None
     smallest = np.argsort(synth.doc_lengths(w), kind="stable")
-    threads = min(os.cpu_count() or 1, 16)
+    if threads is None:
+        threads = min(os.cpu_count() or 1, 16)
     points, notes = [], []
     for S in (32, 256):
         texts = [synth.dna_docs(w, first=int(d), count=1).bytes.tobytes() for d in smallest[:S]]
@@ -337,6 +338,13 @@ def main():
     gather_bytes = prof["row_bytes"] / max(prof["launches"], 1)
     achieved = gather_bytes / (gather_ms * 1e-3) / 1e9
 
+    # the device's read ceiling beside it: a plain coalesced read of 8 GiB
+    rbuf = torch.empty(8 << 30, dtype=torch.uint8, device="cuda")
+    cobs.read_bandwidth(rbuf)
+    stream_read = max(cobs.read_bandwidth(rbuf) for _ in range(3))
+    del rbuf
+    log(f"read ceiling {stream_read:.0f} GB/s")
+
     # top-k run of the same set (K = 0, top-100)
     topk_ms = None
     if w.topk:
@@ -371,6 +379,10 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         cpu = cpu_baseline(w, synth, oracle, qs, args.cpu_seconds)
+        one = cpu_baseline(w, synth, oracle, qs, args.cpu_seconds / 2, threads=1)
+        if cpu and one:
+            cpu["value_1_thread"] = one["value"]
+            cpu["sample_1_thread"] = one["sample"]
         log("cpu baseline done")
 
     offload = None
@@ -404,6 +416,7 @@ def main():
                    "host_link_GBps": info["total_bytes"] / (ogather * 1e-3) / 1e9}
         log(f"offloaded: {offload}")
 
+    traffic = committed_traffic(w.name)
     out = {
         "metric": "k-mer lookups/s (distinct query terms scored against every document) "
                   "+ row-gather HBM GB/s",
@@ -428,8 +441,14 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS, "traffic": committed_traffic(w.name),
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
         },
+        "hbm": {
+            "stream_read_GBps": stream_read,
+            "gather_frac_of_stream_read": achieved / stream_read,
+            "gather_counted_GBps": traffic / (gather_ms * 1e-3) / 1e9 if traffic else None,
+        },
+        "row_fetches_per_s": value * w.h * info["n_blocks"],
         "gather_kernel_ms": gather_ms,
         "host_input_ms_per_step": host_step_ms,
         "tuning": tuning,

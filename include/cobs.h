@@ -525,6 +525,18 @@ typedef struct {
 } cobs_kernel_timing;
 
 cobs_status cobs_profile(int enable);
+
+/*
+ * Read ceiling of the device: two passes of coalesced, non-temporal 16-byte
+ * loads over [buf, buf + bytes) by a persistent grid (each wavefront reading
+ * contiguous 64 KiB chunks; the whole grid sweeping the buffer), each timed
+ * with HIP events on `stream`; *gbps = bytes / the faster pass's time
+ * (10^9 B/s).  The gather kernel's
+ * row reads are judged against it beside the HBM peak.  buf: device memory,
+ * 16-byte aligned, only read (its contents do not matter); bytes: a positive
+ * multiple of 16.  Errors: EINVAL, EDEVICE.
+ */
+cobs_status cobs_read_bandwidth(const void *buf, uint64_t bytes, void *stream, double *gbps);
 cobs_status cobs_profile_read(cobs_kernel_timing *gather, int reset);
 
 /* ---- misc --------------------------------------------------------------- */

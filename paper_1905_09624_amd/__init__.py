@@ -147,6 +147,8 @@ EXPORTS = {
                             C.c_void_p, C.POINTER(Tuning)]),
     "cobs_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
     "cobs_profile": (C.c_int, [C.c_int]),
+    "cobs_read_bandwidth": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p,
+                                      C.POINTER(C.c_double)]),
     "cobs_profile_read": (C.c_int, [C.POINTER(KernelTiming), C.c_int]),
     "cobs_last_error": (C.c_char_p, []),
     "cobs_now_ns": (C.c_uint64, []),
@@ -568,6 +570,15 @@ def use_torch_allocator(enable: bool = True) -> None:
 
 def now_ns() -> int:
     return int(lib().cobs_now_ns())
+
+
+def read_bandwidth(tensor, stream=None) -> float:
+    """GB/s of one coalesced read pass over a device tensor (cobs_read_bandwidth)."""
+    gbps = C.c_double()
+    nbytes = tensor.numel() * tensor.element_size() // 16 * 16
+    _check(lib().cobs_read_bandwidth(C.c_void_p(tensor.data_ptr()), nbytes, _stream(stream),
+                                     C.byref(gbps)))
+    return gbps.value
 
 
 def profile(enable: bool) -> None:

@@ -165,6 +165,14 @@ hipError_t launch_insert(const uint8_t *bytes, const StrDesc *strs, uint32_t n_s
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st);
 
+// One read pass over bytes / 16 16-byte words at p (16-byte aligned) by
+// kReadGrid workgroups of 256 threads; pattern 0: per-wavefront chunks of
+// kReadChunk words, 1: grid-wide sweep.  sink: kReadGrid words, written only
+// in the improbable case that keeps the loads alive.
+constexpr uint32_t kReadGrid = 2048;
+constexpr uint64_t kReadChunk = 4096;
+hipError_t launch_read(const void *p, uint64_t bytes, int pattern, uint32_t *sink, hipStream_t st);
+
 // Classic merge: every row of out (out_stride bytes) = the na document bits
 // of a's row, then b's row bits; strides are multiples of 4.
 hipError_t launch_concat_rows(const uint8_t *a, uint64_t a_stride, uint32_t na, const uint8_t *b,

@@ -785,6 +785,36 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
     return COBS_OK;
 }
 
+cobs_status cobs_read_bandwidth(const void *buf, uint64_t bytes, void *stream, double *gbps)
+{
+    if (!buf || !gbps) return set_error(COBS_EINVAL, "NULL argument");
+    if (((uintptr_t)buf & 15u) || (bytes & 15u) || bytes == 0)
+        return set_error(COBS_EINVAL, "buffer must be 16-byte aligned, bytes a positive multiple of 16");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf sink;
+    COBS_HIP(sink.ensure((size_t)kReadGrid * 4));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    cobs_status s = COBS_OK;
+    float ms = 0.f;
+    for (hipEvent_t &e : ev)
+        if (s == COBS_OK && hipEventCreate(&e) != hipSuccess) s = set_error(COBS_EDEVICE, "hipEventCreate");
+    float best = 0.f;
+    for (int pattern = 0; pattern < 2 && s == COBS_OK; ++pattern) {
+        hipError_t e = hipEventRecord(ev[0], st);
+        if (e == hipSuccess) e = launch_read(buf, bytes, pattern, sink.as<uint32_t>(), st);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) s = hip_error(e, "read pass");
+        else if (ms > 0.f && (best == 0.f || ms < best)) best = ms;
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s != COBS_OK) return s;
+    *gbps = best > 0.f ? (double)bytes / (best * 1e-3) / 1e9 : 0.0;
+    return COBS_OK;
+}
+
 cobs_status cobs_profile(int enable)
 {
     g_prof.store(enable ? 1 : 0);
