@@ -47,6 +47,18 @@ def test_binding_covers_abi(built_lib):
     cobs.lib()
 
 
+def test_header_is_plain_c(tmp_path):
+    # the boundary is a C ABI: the header compiles as strict C99, with no torch
+    # or C++ types, and every declared function is callable from C
+    src = tmp_path / "use.c"
+    calls = "\n".join(f"    (void)&{f};" for f in declared_functions())
+    src.write_text('#include "cobs.h"\nint main(void)\n{\n' + calls + "\n    return 0;\n}\n")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I", os.path.join(ROOT, "include"), "-c", str(src), "-o",
+                        str(tmp_path / "use.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_allocator_needs_a_free_function(built_lib):
     # host-side argument check of cobs_set_allocator (no device memory touched)
     import paper_1905_09624_amd as cobs
