@@ -382,6 +382,9 @@ void cobs_results_free(cobs_results *r);
  *  max_batch_terms     windows per batch before it is cut, 0 = 2^23 (a
  *                      longer request still runs, as a batch of its own)
  *  score_bits          16 or 32 (0 = 32)
+ *  max_inflight        most requests admitted at once (each holds one score
+ *                      buffer), 0 = as many as the budget holds; the pool
+ *                      holds min(budget / score_bytes, max_inflight) buffers
  */
 typedef struct {
     uint64_t score_budget_bytes;
@@ -389,7 +392,7 @@ typedef struct {
     uint32_t max_batch_queries;
     uint64_t max_batch_terms;
     uint32_t score_bits;
-    uint32_t reserved;
+    uint32_t max_inflight;
 } cobs_serve_opts;
 
 typedef struct {

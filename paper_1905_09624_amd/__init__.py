@@ -63,7 +63,7 @@ class Hits(C.Structure):
 class ServeOpts(C.Structure):
     _fields_ = [("score_budget_bytes", C.c_uint64), ("num_streams", C.c_uint32),
                 ("max_batch_queries", C.c_uint32), ("max_batch_terms", C.c_uint64),
-                ("score_bits", C.c_uint32), ("reserved", C.c_uint32)]
+                ("score_bits", C.c_uint32), ("max_inflight", C.c_uint32)]
 
 
 class ServeStats(C.Structure):
@@ -443,10 +443,10 @@ class Server:
     """Continuous-batching server over a resident index (cobs_serve)."""
 
     def __init__(self, index: Index, budget_bytes=0, num_streams=0, max_batch_queries=0,
-                 max_batch_terms=0, score_bits=32):
+                 max_batch_terms=0, score_bits=32, max_inflight=0):
         self.index = index
         opts = ServeOpts(budget_bytes, num_streams, max_batch_queries, max_batch_terms,
-                         score_bits, 0)
+                         score_bits, max_inflight)
         self._h = C.c_void_p()
         _check(lib().cobs_serve(index._h, C.byref(opts), C.byref(self._h)))
 

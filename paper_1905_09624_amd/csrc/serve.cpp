@@ -191,6 +191,7 @@ cobs_status cobs_serve(cobs_index *ix, const cobs_serve_opts *opts, cobs_server 
         budget = std::min<uint64_t>(4096 * slot_bytes, fr / 4);
     }
     s->n_slots = std::min<uint64_t>(budget / slot_bytes, 1u << 30);
+    if (s->opts.max_inflight) s->n_slots = std::min<uint64_t>(s->n_slots, s->opts.max_inflight);
     auto fail = [&](cobs_status st) {
         for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
         for (Workspace *w : s->spaces) delete w;

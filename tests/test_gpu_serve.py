@@ -101,6 +101,14 @@ def test_admission_by_score_memory(served):
     batch = ix.query(qs.bytes[: int(qs.q_off[12])], qs.q_off[:13], k=(1, 2))
     for a, b in zip(res, batch):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # one request admitted at a time (max_inflight): every batch holds exactly one
+    srv = cobs.Server(ix, num_streams=2, max_inflight=1)
+    tickets = [srv.submit(qs.get(i), k=(1, 2)) for i in range(12)]
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stop()
+    assert st["completed"] == 12 and st["batches"] == 12
+    for a, b in zip(res, batch):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
 def test_open_loop_replay_and_stats(served):
