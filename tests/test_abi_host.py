@@ -59,6 +59,56 @@ def test_header_is_plain_c(tmp_path):
     assert r.returncode == 0, r.stderr
 
 
+C_PROGRAM = r"""
+#include <stdio.h>
+#include <string.h>
+#include "cobs.h"
+
+int main(void)
+{
+    const char *fa = ">r1 first read\nACGT\nAC\n>r2\nTTTT\n";
+    const char *fq = "@q\nACGTN\n+\nIIIII\n";
+    cobs_docset *ds = NULL;
+    cobs_docs docs;
+    if (cobs_docset_create(&ds) != COBS_OK) return 1;
+    if (cobs_docset_add_buffer(ds, (const uint8_t *)fa, strlen(fa), COBS_FORMAT_MULTI_FASTA) != COBS_OK) return 2;
+    if (cobs_docset_add_buffer(ds, (const uint8_t *)fq, strlen(fq), COBS_FORMAT_FASTQ) != COBS_OK) return 3;
+    if (cobs_docset_add_buffer(ds, (const uint8_t *)"@x\nAC\n", 7, COBS_FORMAT_FASTQ) != COBS_EINVAL) return 4;
+    printf("error: %s\n", cobs_last_error());
+    if (cobs_docset_view(ds, &docs) != COBS_OK) return 5;
+    printf("docs %u strings %llu bytes %llu\n", docs.n_docs,
+           (unsigned long long)docs.doc_str[docs.n_docs],
+           (unsigned long long)docs.str_off[docs.doc_str[docs.n_docs]]);
+    for (uint32_t d = 0; d < docs.n_docs; ++d)
+        for (uint64_t i = docs.doc_str[d]; i < docs.doc_str[d + 1]; ++i)
+            printf("doc %u: %.*s\n", d, (int)(docs.str_off[i + 1] - docs.str_off[i]),
+                   (const char *)docs.bytes + docs.str_off[i]);
+    cobs_docset_free(ds);
+    if (cobs_set_allocator(NULL) != COBS_OK) return 6;
+    return 0;
+}
+"""
+
+
+def test_c_program_links_and_calls_the_library(built_lib, tmp_path):
+    # a plain C program linked against libcobs.so uses the host-side entry
+    # points (document sets from FASTA/FASTQ buffers, errors) without Python
+    src = tmp_path / "prog.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "prog"
+    libdir = os.path.dirname(built_lib)
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        str(src), "-o", str(exe), "-L", libdir, "-lcobs",
+                        "-Wl,-rpath," + libdir], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    lines = r.stdout.splitlines()
+    assert lines[0].startswith("error: ") and "FASTQ" in lines[0]
+    assert lines[1] == "docs 3 strings 3 bytes 15"
+    assert lines[2:] == ["doc 0: ACGTAC", "doc 1: TTTT", "doc 2: ACGTN"]
+
+
 def test_allocator_needs_a_free_function(built_lib):
     # host-side argument check of cobs_set_allocator (no device memory touched)
     import paper_1905_09624_amd as cobs
