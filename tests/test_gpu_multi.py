@@ -113,6 +113,14 @@ def test_multi_equals_the_merged_index():
         for x, y in zip(cobs.query_multi([ia, ib], ddata, off, k=k, topk=topk),
                         merged.query(data, off, k=k, topk=topk)):
             assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) and x[2] == y[2]
+    # one part kept in host memory and streamed, the other in HBM
+    big = max(ib.block(b)["rows"] * ib.block(b)["stride"] for b in range(ib.info()["n_blocks"]))
+    ib.offload(2 * ((big + 255) // 256 * 256))
+    try:
+        for x, y in zip(cobs.query_multi([ia, ib], data, off, k=(1, 2)), merged.query(data, off, k=(1, 2))):
+            assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) and x[2] == y[2]
+    finally:
+        ib.onload()
 
 
 def test_multi_refuses_mixed_term_definitions(parts):
