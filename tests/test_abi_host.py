@@ -117,6 +117,22 @@ def test_allocator_needs_a_free_function(built_lib):
     assert cobs.lib().cobs_set_allocator(None) == cobs.OK
 
 
+def test_product_path_fails_loudly_without_the_library():
+    # with libcobs.so absent every entry point raises; nothing falls back
+    code = ("import numpy as np, paper_1905_09624_amd as c\n"
+            "c.LIB_PATH = '/nonexistent/libcobs.so'\n"
+            "prm = c.make_params(0, 31, True, 1, 0.3, 0, 1)\n"
+            "d = np.frombuffer(b'ACGT' * 20, np.uint8)\n"
+            "try:\n"
+            "    c.Index.build(prm, d, np.array([0, 80], np.uint64), np.array([0, 1], np.uint64))\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "not built" in r.stdout
+
+
 def test_library_does_not_link_the_oracle(built_lib):
     out = subprocess.check_output(["nm", "-D", built_lib]).decode()
     assert "orc_" not in out
