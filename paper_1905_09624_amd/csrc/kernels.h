@@ -123,9 +123,11 @@ uint64_t dedup_table_cap(uint64_t windows);    // hash-set capacity for a query 
 uint64_t dedup_table_slots(uint64_t windows);  // global slots (0: LDS table)
 uint32_t dedup_groups(uint64_t windows);       // workgroups of the query
 // Per-query chunks, thresholds, score-buffer slots, work totals; zeroes
-// counters.  qorder: the queries by size class, largest first (work items
-// follow that order); chunk_prefix[i]: first chunk of query qorder[i].  A query split into several chunks uses score buffer slot[i] when
-// slot is non-NULL, else the next free one in query order.
+// counters.
+// qorder: the queries by size class, largest first (work items follow that
+// order); chunk_prefix[i]: first chunk of query qorder[i].  A query split
+// into several chunks uses score buffer slot[i] when slot is non-NULL, else
+// the next free one in query order.
 hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, const uint32_t *slot,
                        uint32_t n_queries, uint32_t chunk, uint32_t n_slices, uint32_t k_num,
                        uint32_t k_den, uint64_t ell_limit, QInfo *qinfo, uint32_t *qorder,
@@ -135,12 +137,16 @@ hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, const uint
 
 // a5-a8: persistent gather / AND / ADD / threshold-or-top-k kernel.
 // planes: counter planes (>= bits of the largest l); unroll: terms whose rows
-// are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4).
-hipError_t launch_gather(const GatherArgs &a, int planes, int unroll, int grid, hipStream_t st);
+// are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4).  packed: every
+// slice of a.slices is at most kPackedSliceBytes wide, and 2, 4 or 8 terms
+// share one load (64 / G lanes each, G from the slice's width).
+constexpr uint32_t kPackedSliceBytes = 512;
+hipError_t launch_gather(const GatherArgs &a, int planes, int unroll, int grid, bool packed,
+                         hipStream_t st);
 int gather_planes_for(uint64_t max_terms);        // instantiated plane count to use
 int gather_default_unroll(int h);
 bool gather_unroll_valid(int unroll, int h);
-int gather_grid(int planes, int unroll, int h);   // persistent grid: CUs x resident blocks
+int gather_grid(int planes, int unroll, int h, bool packed);   // persistent grid: CUs x resident blocks
 
 // a8+a9 ordering: group candidates by query and sort each query's segment by
 // (score desc, input id asc); write the first min(count, topk) hits.

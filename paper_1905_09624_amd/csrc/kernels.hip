@@ -530,8 +530,11 @@ struct Counter {
     }
 };
 
-// U: terms whose rows are in flight per wavefront (h rows each)
-template <int P, int U, bool kH1>
+// U: terms whose rows are in flight per wavefront (h rows each).
+// kPacked: every slice of the launch is narrow (at most 512 bytes wide); G =
+// 2, 4 or 8 terms share one load, 64 / G lanes each, and the G partial
+// counts of every document are summed at the end of the item.
+template <int P, int U, bool kH1, bool kPacked>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 {
     const uint32_t lane = lane_id();
@@ -564,11 +567,18 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
         const uint32_t sstride = uniform_u32(sd.stride);
         const uint32_t srows = uniform_u32(sd.rows);
         const uint32_t swidth = uniform_u32(sd.width);
-        // every lane loads (no divergent loads: they serialise the memory
-        // pipeline); lanes past the slice width read an in-row address and
-        // mask the bits off
-        const uint32_t loff = min(lane * 16u, swidth - 16u);
-        const uint32_t lmask = lane * 16u < swidth ? ~0u : 0u;
+        // lanes per term (lpt) and this lane's term group and column; every
+        // lane loads (no divergent loads: they serialise the memory pipeline);
+        // lanes past the slice width read an in-row address and mask the
+        // bits off
+        uint32_t lpt = 64u, grp = 0u, col = lane;
+        if constexpr (kPacked) {
+            lpt = swidth <= 128u ? 8u : (swidth <= 256u ? 16u : 32u);
+            grp = lane / lpt;
+            col = lane & (lpt - 1u);
+        }
+        const uint32_t loff = min(col * 16u, swidth - 16u);
+        const uint32_t lmask = col * 16u < swidth ? ~0u : 0u;
         const uint8_t *mrow0 = a.matrix + sbase + loff;
         const uint64_t *hp = a.hashes + qn.hbase * a.h;
 
@@ -584,6 +594,31 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
                     for (int i = 0; i < kMaxHashes; ++i)
                         if (i < (int)a.h) r[i] = (uint32_t)(hp[(uint64_t)(k0 + lane) * a.h + i] % srows);
                 }
+            }
+            if constexpr (kPacked) {
+                // group g takes terms j + g, j + G + g, ...; terms past n
+                // repeat the last row and are masked off
+                const uint32_t G = 64u / lpt;
+                for (uint32_t j = 0; j < n; j += G * U) {
+                    u32x4 v[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const uint32_t t = min(j + G * (uint32_t)u + grp, n - 1);
+                        v[u] = load_row<kH1>(mrow0 + (uint64_t)(uint32_t)__shfl((int)r[0], (int)t, 64) * sstride);
+                        if (!kH1) {
+#pragma unroll
+                            for (int i = 1; i < kMaxHashes; ++i)
+                                if (i < (int)a.h)
+                                    v[u] &= load_row<kH1>(
+                                        mrow0 + (uint64_t)(uint32_t)__shfl((int)r[i], (int)t, 64) * sstride);
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) v[u] &= (j + G * (uint32_t)u + grp < n) ? lmask : 0u;
+                    cnt.template add<U>(v);
+                }
+                continue;
             }
             for (uint32_t j = 0; j < n; j += U) {
                 // a short last group repeats its last row (already in flight,
@@ -607,6 +642,27 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
                 for (int u = 0; u < U; ++u) v[u] &= ((uint32_t)u < rem) ? lmask : 0u;
                 cnt.template add<U>(v);
             }
+        }
+
+        // packed: lanes c, c + lpt, c + 2 lpt, ... hold partial counts of the
+        // same 128 documents; butterfly rounds of bit-plane additions leave
+        // the sums in every lane, then lanes from lpt on drop theirs (each
+        // partial count is at most l < 2^P, so no carry leaves plane P - 1)
+        if constexpr (kPacked) {
+            for (uint32_t m = 32u; m >= lpt; m >>= 1) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    uint32_t carry = 0;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const uint32_t x = cnt.H[p][d];
+                        const uint32_t y = (uint32_t)__shfl_xor((int)x, (int)m, 64);
+                        cnt.H[p][d] = x ^ y ^ carry;
+                        carry = (x & y) | (carry & (x ^ y));
+                    }
+                }
+            }
+            if (lane >= lpt) cnt.clear();
         }
 
         // Several chunks of one (query, slice): each adds its counts into the
@@ -1081,36 +1137,51 @@ int grid_for(uint64_t n, int block)
 
 // Instantiated variants: h = 1 with 4 or 8 terms in flight, h > 1 with 2 or
 // 4 (each term then has h rows in flight).
-template <int P>
-hipError_t launch_gather_p(const GatherArgs &a, int unroll, int grid, hipStream_t st)
+template <int P, bool kPacked>
+hipError_t launch_gather_pk(const GatherArgs &a, int unroll, int grid, hipStream_t st)
 {
     if (a.h == 1) {
         if (unroll == 8)
-            hipLaunchKernelGGL((gather_kernel<P, 8, true>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((gather_kernel<P, 8, true, kPacked>), dim3(grid), dim3(256), 0, st, a);
         else
-            hipLaunchKernelGGL((gather_kernel<P, 4, true>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((gather_kernel<P, 4, true, kPacked>), dim3(grid), dim3(256), 0, st, a);
     } else {
         if (unroll == 4)
-            hipLaunchKernelGGL((gather_kernel<P, 4, false>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((gather_kernel<P, 4, false, kPacked>), dim3(grid), dim3(256), 0, st, a);
         else
-            hipLaunchKernelGGL((gather_kernel<P, 2, false>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((gather_kernel<P, 2, false, kPacked>), dim3(grid), dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }
 
 template <int P>
-int occ_of_p(int unroll, int h)
+hipError_t launch_gather_p(const GatherArgs &a, int unroll, int grid, bool packed, hipStream_t st)
+{
+    return packed ? launch_gather_pk<P, true>(a, unroll, grid, st)
+                  : launch_gather_pk<P, false>(a, unroll, grid, st);
+}
+
+template <int P, bool kPacked>
+int occ_of_pk(int unroll, int h)
 {
     int blocks = 0;
     hipError_t e;
     if (h == 1)
-        e = unroll == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 8, true>, 256, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 4, true>, 256, 0);
+        e = unroll == 8
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 8, true, kPacked>, 256, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 4, true, kPacked>, 256, 0);
     else
-        e = unroll == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 4, false>, 256, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 2, false>, 256, 0);
+        e = unroll == 4
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 4, false, kPacked>, 256, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 2, false, kPacked>, 256, 0);
     if (e != hipSuccess || blocks < 1) blocks = 1;
     return blocks;
+}
+
+template <int P>
+int occ_of_p(int unroll, int h, bool packed)
+{
+    return packed ? occ_of_pk<P, true>(unroll, h) : occ_of_pk<P, false>(unroll, h);
 }
 
 }  // namespace
@@ -1195,22 +1266,23 @@ bool gather_unroll_valid(int unroll, int h)
     return h == 1 ? (unroll == 4 || unroll == 8) : (unroll == 2 || unroll == 4);
 }
 
-hipError_t launch_gather(const GatherArgs &a, int planes, int unroll, int grid, hipStream_t st)
+hipError_t launch_gather(const GatherArgs &a, int planes, int unroll, int grid, bool packed,
+                         hipStream_t st)
 {
     switch (planes) {
-    case 8: return launch_gather_p<8>(a, unroll, grid, st);
-    case 10: return launch_gather_p<10>(a, unroll, grid, st);
-    case 12: return launch_gather_p<12>(a, unroll, grid, st);
-    case 14: return launch_gather_p<14>(a, unroll, grid, st);
-    case 16: return launch_gather_p<16>(a, unroll, grid, st);
-    case 20: return launch_gather_p<20>(a, unroll, grid, st);
-    case 24: return launch_gather_p<24>(a, unroll, grid, st);
-    case 32: return launch_gather_p<32>(a, unroll, grid, st);
+    case 8: return launch_gather_p<8>(a, unroll, grid, packed, st);
+    case 10: return launch_gather_p<10>(a, unroll, grid, packed, st);
+    case 12: return launch_gather_p<12>(a, unroll, grid, packed, st);
+    case 14: return launch_gather_p<14>(a, unroll, grid, packed, st);
+    case 16: return launch_gather_p<16>(a, unroll, grid, packed, st);
+    case 20: return launch_gather_p<20>(a, unroll, grid, packed, st);
+    case 24: return launch_gather_p<24>(a, unroll, grid, packed, st);
+    case 32: return launch_gather_p<32>(a, unroll, grid, packed, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-int gather_grid(int planes, int unroll, int h)
+int gather_grid(int planes, int unroll, int h, bool packed)
 {
     static int cus = 0;
     if (!cus) {
@@ -1221,14 +1293,14 @@ int gather_grid(int planes, int unroll, int h)
     }
     int occ = 1;
     switch (planes) {
-    case 8: occ = occ_of_p<8>(unroll, h); break;
-    case 10: occ = occ_of_p<10>(unroll, h); break;
-    case 12: occ = occ_of_p<12>(unroll, h); break;
-    case 14: occ = occ_of_p<14>(unroll, h); break;
-    case 16: occ = occ_of_p<16>(unroll, h); break;
-    case 20: occ = occ_of_p<20>(unroll, h); break;
-    case 24: occ = occ_of_p<24>(unroll, h); break;
-    default: occ = occ_of_p<32>(unroll, h); break;
+    case 8: occ = occ_of_p<8>(unroll, h, packed); break;
+    case 10: occ = occ_of_p<10>(unroll, h, packed); break;
+    case 12: occ = occ_of_p<12>(unroll, h, packed); break;
+    case 14: occ = occ_of_p<14>(unroll, h, packed); break;
+    case 16: occ = occ_of_p<16>(unroll, h, packed); break;
+    case 20: occ = occ_of_p<20>(unroll, h, packed); break;
+    case 24: occ = occ_of_p<24>(unroll, h, packed); break;
+    default: occ = occ_of_p<32>(unroll, h, packed); break;
     }
     return cus * occ;
 }

@@ -517,6 +517,8 @@ cobs_status upload_layout(cobs_index *ix, hipStream_t st)
     if (!ix->slices.empty())
         COBS_HIP(hipMemcpyAsync(ix->d_slices, ix->slices.data(), ix->slices.size() * sizeof(SliceDesc),
                                 hipMemcpyHostToDevice, st));
+    ix->packed = !ix->slices.empty();
+    for (const SliceDesc &sd : ix->slices) ix->packed = ix->packed && sd.width <= kPackedSliceBytes;
     return COBS_OK;
 }
 

@@ -123,7 +123,7 @@ static cobs_status gather_streamed(cobs_index *ix, Workspace &ws, GatherArgs ga,
         a.slices = ix->d_group_slices + gr.slice0;
         a.n_slices = gr.n_slices;
         a.work_counter = counters + g;
-        COBS_HIP(launch_gather(a, planes, unroll, grid, st));
+        COBS_HIP(launch_gather(a, planes, unroll, grid, false, st));
         COBS_HIP(hipEventRecord(ix->ev_done[g % 2], st));
         if (g + 2 < G) {
             cobs_status c = copy(g + 2);
@@ -196,7 +196,13 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     const int planes = gather_planes_for(maxw);
     int unroll = b.unroll ? (int)b.unroll : (ix->tuned_unroll ? ix->tuned_unroll : gather_default_unroll((int)h));
     if (!gather_unroll_valid(unroll, (int)h)) unroll = gather_default_unroll((int)h);
-    int grid = gather_grid(planes, unroll, (int)h);
+    // An index whose slices are all narrow (blocks of at most 4,096
+    // documents) is gathered by the packed kernel, several terms per load;
+    // where wide slices carry most of the bytes, the narrow ones ride along
+    // in the same launch (a separate packed launch measured slower there).
+    // An offloaded index streams through the plain kernel.
+    const bool packed = ix->packed && !ix->h_matrix;
+    int grid = gather_grid(planes, unroll, (int)h, packed);
     const uint32_t cap = b.chunk_cap ? b.chunk_cap : (ix->tuned_chunk ? ix->tuned_chunk : kDefaultChunkCap);
     const uint32_t C = b.chunk ? b.chunk : auto_chunk(W, n_slices, grid, cap);
     uint64_t pslots = 0, items = 0;
@@ -343,7 +349,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
                 if (!e) COBS_HIP(hipEventCreate(&e));
             COBS_HIP(hipEventRecord(ws.ev[0], st));
         }
-        if (n_slices && !ix->h_matrix) COBS_HIP(launch_gather(ga, planes, unroll, grid, st));
+        if (n_slices && !ix->h_matrix) COBS_HIP(launch_gather(ga, planes, unroll, grid, packed, st));
         if (n_slices && ix->h_matrix) {
             cobs_status gs = gather_streamed(ix, ws, ga, planes, unroll, grid, st);
             if (gs != COBS_OK) return gs;

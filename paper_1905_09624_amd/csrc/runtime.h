@@ -118,6 +118,9 @@ struct cobs_index {
     uint64_t total_bytes = 0;
     uint32_t *d_order = nullptr;
     cobs::SliceDesc *d_slices = nullptr;
+    // every slice is at most kPackedSliceBytes wide: the matrix in HBM is
+    // gathered by the packed kernel (several terms per load)
+    bool packed = false;
     cobs::Seeds seeds{};
     int tuned_unroll = 0;              // set by cobs_tune (0 = default)
     uint32_t tuned_chunk = 0;          // set by cobs_tune (0 = automatic)
