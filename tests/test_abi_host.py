@@ -232,6 +232,20 @@ def test_arrivals_are_poisson():
     assert abs(gaps.std() - 1e-3) < 1e-4
 
 
+def test_bench_reads_traffic_only_for_the_current_kernel(tmp_path, monkeypatch):
+    # roofline.traffic comes from the committed counter summary, and only
+    # while the kernel source it was taken with is unchanged
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.committed_traffic("text-50k") is None          # another workload
+    t = bench.committed_traffic("compact-100k")
+    assert t is None or t > 266_739_329_024                     # at least the rows it must read
+    changed = tmp_path / "kernels.hip"
+    changed.write_bytes(open(bench.KERNEL_SOURCE, "rb").read() + b"\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(changed))
+    assert bench.committed_traffic("compact-100k") is None
+
+
 def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
