@@ -201,6 +201,12 @@ CASES = [
     dict(kind=DNA, q=4, canonical=True, h=3, p=0.5, B=1),
     dict(kind=DNA, q=7, canonical=True, h=1, p=0.3, B=7),
     dict(kind=BYTES, q=3, canonical=False, h=2, p=0.2, B=4),
+    # the corners of the accepted ranges
+    dict(kind=DNA, q=1, canonical=False, h=5, p=0.9, B=2),
+    dict(kind=DNA, q=2, canonical=True, h=8, p=0.01, B=0),
+    dict(kind=DNA, q=31, canonical=True, h=4, p=0.3, B=3),
+    dict(kind=BYTES, q=1, canonical=False, h=8, p=0.5, B=1),
+    dict(kind=BYTES, q=8, canonical=False, h=6, p=0.1, B=5),
 ]
 
 
