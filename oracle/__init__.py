@@ -86,6 +86,10 @@ def lib():
                                                 vp, u64, vp]),
                 "orc_exact_intersection": (u64, [C.POINTER(_Params), vp, vp, vp, u32,
                                                  vp, u64, vp]),
+                "orc_term_rows": (None, [C.POINTER(_Params), u64, vp, u64, vp]),
+                "orc_doc_scores": (None, [C.POINTER(_Params), u64, vp, vp, u64, vp, u64, vp, u32,
+                                          vp]),
+                "orc_rc_palindrome_dups": (u64, [u32, vp, u64, C.POINTER(u64)]),
                 "orc_n_blocks": (u32, [vp]),
                 "orc_block_info": (None, [vp, u32, vp, vp, vp, vp, vp]),
                 "orc_order": (vp, [vp]),
@@ -306,3 +310,59 @@ def exact_intersection(docs: Docs, query, kind=DNA, q=31, canonical=True):
                                      _ptr(docs.str_off), _ptr(docs.doc_str),
                                      docs.n_docs, _ptr(qb), len(query), _ptr(out))
     return out[: docs.n_docs], int(l)
+
+
+# ---- one document at a time --------------------------------------------------
+
+class QuerySet:
+    """Distinct terms of each query and their rows at a filter size m, for
+    scoring documents one by one (block and column separability, section 2.2):
+    a document's score depends only on its own terms, m and the query."""
+
+    def __init__(self, queries, kind=DNA, q=31, canonical=True, h=1, p=0.3, seed=0):
+        self.params = _Params(kind, q, int(canonical), h, p, 0, seed, 128)
+        per = [unique(terms(kind, q, canonical, x)) for x in queries]
+        self.ell = np.array([len(t) for t in per], np.uint64)
+        self.off = np.zeros(len(per) + 1, np.uint64)
+        np.cumsum(self.ell, out=self.off[1:])
+        self.terms = np.concatenate(per).astype(np.uint64) if per else np.zeros(0, np.uint64)
+        self.total = int(self.off[-1])
+        self._rows = {}
+
+    def rows(self, m: int) -> np.ndarray:
+        if m not in self._rows:
+            out = np.zeros(max(self.params.h * self.total, 1), np.uint64)
+            src = self.terms if self.total else np.zeros(1, np.uint64)
+            lib().orc_term_rows(C.byref(self.params), m, _ptr(src), self.total, _ptr(out))
+            self._rows[m] = out
+        return self._rows[m]
+
+    def doc_scores(self, m: int, strings) -> np.ndarray:
+        """Scores of the document made of `strings` at filter size m."""
+        if isinstance(strings, np.ndarray):
+            data = _bytes(strings)
+            so = np.array([0, strings.size], np.uint64)
+            n_str = 1
+        else:
+            if isinstance(strings, (bytes, bytearray)):
+                strings = [strings]
+            parts = [bytes(x) for x in strings]
+            data = _bytes(b"".join(parts))
+            so = np.zeros(len(parts) + 1, np.uint64)
+            np.cumsum([len(x) for x in parts], out=so[1:])
+            n_str = len(parts)
+        nq = len(self.ell)
+        out = np.zeros(max(nq, 1), np.uint32)
+        rows = self.rows(m)
+        lib().orc_doc_scores(C.byref(self.params), m, _ptr(data), _ptr(so), n_str, _ptr(rows),
+                             self.total, _ptr(self.off), nq, _ptr(out))
+        return out[:nq]
+
+
+def rc_palindrome_dups(q: int, s) -> tuple[int, int]:
+    """(windows of s repeating an earlier window as its reverse complement
+    through a palindrome, valid windows) for canonical DNA q-mers."""
+    b = _bytes(s)
+    v = C.c_uint64()
+    k = lib().orc_rc_palindrome_dups(q, _ptr(b), len(s), C.byref(v))
+    return int(k), int(v.value)

@@ -418,6 +418,129 @@ uint64_t orc_exact_intersection(const orc_params *prm, const uint8_t *bytes,
     return l;
 }
 
+/* ---- one document at a time (block and column separability) ------------- */
+
+void orc_term_rows(const orc_params *prm, uint64_t m, const uint64_t *terms,
+                   uint64_t n, uint64_t *rows)
+{
+    uint64_t st = prm->seed;
+    for (uint32_t i = 0; i < prm->h; ++i) {
+        uint64_t seed_i = orc_splitmix64_next(&st);
+        for (uint64_t x = 0; x < n; ++x)
+            rows[(uint64_t)i * n + x] = orc_mix64(terms[x] ^ seed_i) % m;
+    }
+}
+
+void orc_doc_scores(const orc_params *prm, uint64_t m, const uint8_t *bytes,
+                    const uint64_t *str_off, uint64_t n_str,
+                    const uint64_t *qrows, uint64_t total, const uint64_t *qoff,
+                    uint32_t nq, uint32_t *scores)
+{
+    /* the document's Bloom filter of m bits: bit H_i(t) mod m for every term
+     * t of the document and every i < h (section 2.1) */
+    uint64_t words = (m + 63) / 64;
+    uint64_t *bits = (uint64_t *)calloc(words ? words : 1, sizeof(uint64_t));
+    uint64_t longest = 0;
+    for (uint64_t k = 0; k < n_str; ++k)
+        if (str_off[k + 1] - str_off[k] > longest) longest = str_off[k + 1] - str_off[k];
+    uint64_t *t = (uint64_t *)malloc((longest + 1) * sizeof(uint64_t));
+    uint64_t *seeds = (uint64_t *)malloc((prm->h ? prm->h : 1) * sizeof(uint64_t));
+    hash_seeds(prm->seed, prm->h, seeds);
+    for (uint64_t k = 0; k < n_str; ++k) {
+        uint64_t n = orc_terms(prm->kind, prm->q, prm->canonical, bytes + str_off[k],
+                               str_off[k + 1] - str_off[k], t);
+        for (uint64_t x = 0; x < n; ++x)
+            for (uint32_t i = 0; i < prm->h; ++i) {
+                uint64_t r = orc_mix64(t[x] ^ seeds[i]) % m;
+                bits[r / 64] |= 1ull << (r % 64);
+            }
+    }
+    /* score: query terms whose h bits are all set */
+    for (uint32_t k = 0; k < nq; ++k) {
+        uint32_t c = 0;
+        for (uint64_t x = qoff[k]; x < qoff[k + 1]; ++x) {
+            int all = 1;
+            for (uint32_t i = 0; i < prm->h; ++i) {
+                uint64_t r = qrows[(uint64_t)i * total + x];
+                all &= (int)((bits[r / 64] >> (r % 64)) & 1u);
+            }
+            c += (uint32_t)all;
+        }
+        scores[k] = c;
+    }
+    free(bits); free(t); free(seeds);
+}
+
+static int cmp_u64_plain(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+uint64_t orc_rc_palindrome_dups(uint32_t q, const uint8_t *s, uint64_t len,
+                                uint64_t *valid_windows)
+{
+    signed char *c = (signed char *)malloc(len ? len : 1);
+    uint64_t valid = 0, run = 0;
+    for (uint64_t x = 0; x < len; ++x) {
+        c[x] = (signed char)base_code(s[x]);
+        run = c[x] < 0 ? 0 : run + 1;
+        if (q && run >= q) ++valid;
+    }
+    if (valid_windows) *valid_windows = valid;
+    if (q == 0 || q > 31 || len < q) { free(c); return 0; }
+    uint64_t cap = 64, n = 0;
+    uint64_t *dup = (uint64_t *)malloc(cap * sizeof(uint64_t));
+    /* a window pair needs an arm of at least k = (q + 2) / 2 (at most 16).
+     * Filter: A = the k bases ending at p, s[p] least significant; B = the
+     * complements of the k bases from p + 1, s[p+1] least significant; the
+     * arm reaches k exactly when A == B and those 2k bases are ACGT. */
+    const uint32_t k = (q + 2) / 2;
+    const uint64_t mask = k >= 32 ? ~0ull : (1ull << (2 * k)) - 1;
+    uint64_t A = 0, B = 0;
+    int64_t last_bad = -1;   /* last non-ACGT position among those read */
+    for (uint64_t x = 0; x < len && x < k; ++x) {   /* B for p = -1: bases 0 .. k-1 */
+        int y = c[x];
+        if (y < 0) { last_bad = (int64_t)x; y = 0; }
+        B |= (uint64_t)(3 - y) << (2 * x);
+    }
+    for (uint64_t p = 0; p + 1 < len; ++p) {
+        int y = c[p] < 0 ? 0 : c[p];
+        A = ((A << 2) | (uint64_t)y) & mask;
+        /* B: drop base p, read base p + k */
+        B >>= 2;
+        if (p + k < len) {
+            int z = c[p + k];
+            if (z < 0) { last_bad = (int64_t)(p + k); z = 0; }
+            B |= (uint64_t)(3 - z) << (2 * (k - 1));
+        } else {
+            break;   /* no arm of k bases fits any more */
+        }
+        if (p + 1 < k || A != B || last_bad >= (int64_t)(p + 1 - k)) continue;
+        /* arm: the longest a with s[p-j] the complement of s[p+1+j], j < a */
+        uint64_t a = 0;
+        while (a <= p && p + 1 + a < len) {
+            int u = c[p - a], v = c[p + 1 + a];
+            if (u < 0 || v < 0 || u + v != 3) break;
+            ++a;
+        }
+        /* the palindrome [p+1-h2, p+h2] of length q + d = 2 h2 holds window
+         * i = p+1-h2 and window j = i+d, the reverse complement of window i */
+        for (uint64_t h2 = k; h2 <= a; ++h2) {
+            uint64_t i = p + 1 - h2, d = 2 * h2 - q;
+            if (n == cap) { cap *= 2; dup = (uint64_t *)realloc(dup, cap * sizeof(uint64_t)); }
+            dup[n++] = i + d;
+        }
+    }
+    qsort(dup, n, sizeof(uint64_t), cmp_u64_plain);
+    uint64_t cnt = 0;
+    for (uint64_t x = 0; x < n; ++x)
+        if (x == 0 || dup[x] != dup[x - 1]) ++cnt;
+    free(dup);
+    free(c);
+    return cnt;
+}
+
 /* ---- accessors ---------------------------------------------------------- */
 
 uint32_t orc_n_blocks(const orc_index *ix) { return ix->n_blocks; }

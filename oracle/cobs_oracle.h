@@ -129,6 +129,33 @@ uint64_t orc_exact_intersection(const orc_params *prm, const uint8_t *bytes,
                                 uint32_t n_docs, const uint8_t *query,
                                 uint64_t len, uint32_t *counts);
 
+/* Block and column separability (section 2.2): a document's score depends
+ * only on its own terms, its block's filter size m and the query, so large
+ * collections are checked one document at a time.
+ * orc_term_rows: rows[i * n + x] = H_i(terms[x]) mod m for i < h.
+ * orc_doc_scores: the document made of strings [str_off[k], str_off[k+1])
+ * of bytes, k < n_str, as a Bloom filter of m bits (bit H_i(t) mod m for
+ * every term t and i < h); scores[k] = number of query terms x in
+ * [qoff[k], qoff[k+1]) whose h rows qrows[i * total + x] are all set.  The
+ * query terms must be each query's distinct terms G(P). */
+void orc_term_rows(const orc_params *prm, uint64_t m, const uint64_t *terms,
+                   uint64_t n, uint64_t *rows);
+void orc_doc_scores(const orc_params *prm, uint64_t m, const uint8_t *bytes,
+                    const uint64_t *str_off, uint64_t n_str,
+                    const uint64_t *qrows, uint64_t total, const uint64_t *qoff,
+                    uint32_t nq, uint32_t *scores);
+
+/* DNA string, canonical q-mers: windows j whose term equals that of an
+ * earlier window i of the same string through a reverse-complement
+ * palindrome covering both (window j is the reverse complement of window i;
+ * the windows overlap when j - i < q).  These are the only repeats a
+ * uniform-random string is likely to hold at this length (a hairpin of q + 1
+ * bases around a centre); repeats through a periodic stretch or between
+ * unrelated positions are not found.  *valid_windows: windows without a
+ * non-ACGT byte.  Returns the number of such windows j. */
+uint64_t orc_rc_palindrome_dups(uint32_t q, const uint8_t *s, uint64_t len,
+                                uint64_t *valid_windows);
+
 /* Accessors used by the Python wrapper. */
 uint32_t orc_n_blocks(const orc_index *ix);
 void orc_block_info(const orc_index *ix, uint32_t b, uint32_t *first,

@@ -375,3 +375,72 @@ def test_short_query_document_fpr_matches_theorem1():
             expect += oracle.binom_tail_gt(l, oracle.bloom_fpr(m, 1, int(nt[j])), T - 1)
     rate, want = hits / trials, expect / trials
     assert _sigma_ok(rate, want, trials)
+
+
+# ---- one document at a time ----------------------------------------------------
+
+def _revcomp(s: bytes) -> bytes:
+    return s[::-1].translate(bytes.maketrans(b"ACGT", b"TGCA"))
+
+
+@pytest.mark.parametrize("kind,q,canonical,h,B", [(DNA, 31, True, 1, 0), (DNA, 11, False, 3, 4),
+                                                  (BYTES, 4, False, 2, 0), (BYTES, 8, False, 5, 3)])
+def test_doc_scores_equal_index_columns_and_bruteforce(kind, q, canonical, h, B):
+    # a document's scores from its own terms at its block's filter size equal
+    # its column of the index query and the matrix-free brute force
+    rng = np.random.default_rng(50 + q + h)
+    mk = (lambda n: rand_dna(n, rng, b"ACGTacgtN")) if kind == DNA else \
+        (lambda n: rng.integers(0, 256, n, dtype=np.uint8).tobytes())
+    docs = [[mk(int(rng.integers(0, 300))) for _ in range(int(rng.integers(1, 4)))] for _ in range(11)]
+    d = Docs.from_lists(docs)
+    ix = OracleIndex(d, kind=kind, q=q, canonical=canonical, h=h, p=0.2, B=B, seed=77)
+    qs = [mk(int(rng.integers(q, 400))) for _ in range(5)] + [docs[3][0][:150], b""]
+    qset = oracle.QuerySet(qs, kind=kind, q=q, canonical=canonical, h=h, p=0.2, seed=77)
+    want = [ix.query_scores(x) for x in qs]
+    brute = [oracle.bruteforce_scores(d, x, kind=kind, q=q, canonical=canonical, h=h, p=0.2,
+                                      B=B, seed=77) for x in qs]
+    order = ix.order()
+    for b in range(ix.n_blocks):
+        blk = ix.block(b)
+        for j in range(blk["docs"]):
+            doc = int(order[blk["first"] + j])
+            got = qset.doc_scores(blk["rows"], docs[doc])
+            for k in range(len(qs)):
+                assert got[k] == want[k][0][doc] == brute[k][0][doc], (b, doc, k)
+    assert list(qset.ell) == [w[1] for w in want]
+
+
+def test_rc_palindrome_dups_count_every_overlapping_repeat():
+    # uniform-random strings with planted reverse-complement palindromes
+    # (hairpins): valid windows minus the repeats found = the exact number of
+    # distinct canonical q-mers
+    rng = np.random.default_rng(31)
+    for trial in range(60):
+        q = int(rng.choice([31, 31, 25, 21]))   # far repeats improbable at these lengths
+        parts = []
+        for _ in range(int(rng.integers(1, 6))):
+            parts.append(rand_dna(int(rng.integers(0, 400)), rng))
+            half = rand_dna(int(rng.integers(q // 2, q + 6)), rng)
+            parts.append(half + _revcomp(half))          # palindrome of even length
+            if rng.random() < 0.3:
+                parts.append(b"N")
+        s = b"".join(parts)
+        dups, valid = oracle.rc_palindrome_dups(q, s)
+        exact = len(oracle.unique(oracle.terms(DNA, q, True, s)))
+        assert valid == len(oracle.terms(DNA, q, True, s))
+        assert valid - dups == exact, (trial, q, valid, dups, exact)
+
+
+def test_rc_palindrome_dups_hand_cases():
+    half = b"ACGTTGCAAGGCTTACG"                         # 17 bases
+    s = half + _revcomp(half)                           # 34: windows 0..3 of 31
+    # windows (0, 3) and (1, 2) are reverse complements of each other
+    assert oracle.rc_palindrome_dups(31, s) == (2, 4)
+    assert oracle.rc_palindrome_dups(31, s[1:33]) == (1, 2)  # the centre pair only
+    assert oracle.rc_palindrome_dups(31, s[:32]) == (0, 2)   # off centre: no pair
+    assert oracle.rc_palindrome_dups(31, s[:31]) == (0, 1)
+    # a repeat far apart is not a palindrome: not counted
+    w = rand_dna(31, np.random.default_rng(5))
+    far = w + rand_dna(200, np.random.default_rng(6)) + w
+    dups, valid = oracle.rc_palindrome_dups(31, far)
+    assert dups == 0 and valid - len(oracle.unique(oracle.terms(DNA, 31, True, far))) == 1
