@@ -101,7 +101,7 @@ def build_index_dna(cobs, synth, torch, w, chunk_bytes):
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gather_compact100k_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1905_09624_amd", "csrc", "kernels.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1905_09624_amd", "csrc", "gather.hip")
 
 
 def committed_traffic(workload: str):
@@ -118,7 +118,7 @@ def committed_traffic(workload: str):
             k, v = line[2:].split(": ", 1)
             fields[k.strip()] = v.strip().strip("`")
     src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if fields.get("kernels.hip sha256") != src or fields.get("workload") != workload:
+    if fields.get("gather.hip sha256") != src or fields.get("workload") != workload:
         return None
     try:
         return int(fields["HBM bytes per gather launch"])
@@ -188,12 +188,108 @@ def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, pl
     return out
 
 
+def _timed_lookups(parts, queries, seconds, threads):
+    """Score queries (cycled) against every oracle sub-index in `parts` for
+    about `seconds` on `threads` threads: (distinct terms scored, wall s)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(q):
+        l = 0
+        for ix in parts:
+            l = ix.query_scores(q)[1]
+        return l
+
+    done_l, i = 0, 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        while time.perf_counter() - t0 < seconds:
+            batch = [queries[j % len(queries)] for j in range(i, i + 2 * threads)]
+            done_l += sum(ex.map(one, batch))
+            i += len(batch)
+    return done_l, time.perf_counter() - t0
+
+
+def cpu_baseline_block(w, synth, oracle, qs, order, n_terms, budget_s, threads):
+    """The CPU oracle on the compact index's first block, whole: its 8,192
+    documents (the smallest, in the compact order) as 16 classic oracle
+    sub-indexes of 512 documents built in parallel, each with the block's
+    largest document added so that every sub-index has the block's row count
+    m_0 (the index build is not timed).  Queries of the query set (cycled)
+    are scored against all 16 sub-indexes.  Every call of the oracle's query
+    costs a per-lookup part (terms, sort, hashing) plus a part per document,
+    so the oracle's rate on one index of all 100,000 documents follows from
+    the per-lookup cost a (timed on the block's largest document alone) and
+    the per-document cost b from the whole block on one thread: one lookup
+    costs a + b * 100,000.  The same model predicts the half block (8
+    sub-indexes), which is timed too: the difference is the model's error on
+    this block.  The rate with `threads` threads is the one-thread rate times
+    the speed-up measured over the block."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    B = w.B
+    members = [int(x) for x in order[:B]]
+    big = members[-1]
+    rows = oracle.filter_rows(int(n_terms[big]), w.h, w.p)
+    groups = [members[g * 512:(g + 1) * 512] for g in range(B // 512)]
+    lens = synth.doc_lengths(w)
+
+    def doc(d):
+        out = np.empty(int(lens[d]), np.uint8)
+        synth.lib().synth_doc_bases(w.seed, d, 0, int(lens[d]), synth._p(out))
+        return out.tobytes()
+
+    def build(ids):
+        ix = oracle.OracleIndex(oracle.Docs.from_lists([doc(d) for d in ids]), kind=oracle.DNA,
+                                q=w.q, canonical=w.canonical, h=w.h, p=w.p, B=0,
+                                seed=w.hash_seed)
+        assert ix.block(0)["rows"] == rows
+        return ix, len(ids)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(min(16, threads)) as ex:
+        built = list(ex.map(build, [g if big in g else g + [big] for g in groups] + [[big]]))
+    build_s = time.perf_counter() - t0
+    alone = built.pop()[0]
+    parts = [b[0] for b in built]
+    cols = sum(b[1] for b in built)
+    half = len(parts) // 2
+    half_cols = sum(b[1] for b in built[:half])
+    queries = [qs.get(i) for i in range(qs.n)]
+    l_a, t_a = _timed_lookups([alone], queries, budget_s / 6, 1)
+    l_1, t_1 = _timed_lookups(parts, queries, budget_s / 3, 1)
+    l_h, t_h = _timed_lookups(parts[:half], queries, budget_s / 6, 1)
+    l_n, t_n = _timed_lookups(parts, queries, budget_s / 3, threads)
+    a = t_a / l_a                                   # s per lookup, one call on one document
+    b = (t_1 / l_1 - len(parts) * a) / (cols - len(parts))
+    pred_half = half * a + (half_cols - half) * b
+    err = pred_half / (t_h / l_h) - 1.0
+    rate_1 = 1.0 / (a + b * (w.n_docs - 1))
+    speedup = (l_n / t_n) / (l_1 / t_1)
+    del parts, built, alone
+    return {"value": rate_1 * speedup, "unit": "lookups/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": rate_1,
+            "sample": f"block 0 of the compact plan, whole: its {B} smallest documents as "
+                      f"{len(groups)} classic oracle sub-indexes of 512 (plus the block's largest "
+                      f"document: m_0 = {rows} rows each, {cols} columns), built in parallel in "
+                      f"{build_s:.0f}s (not timed); queries of the set cycled: {l_1 / t_1:.4g} "
+                      f"lookups/s over the block on one thread ({t_1:.0f}s), {l_n / t_n:.4g} on "
+                      f"{threads} ({t_n:.0f}s, speed-up {speedup:.2f}); per lookup a = "
+                      f"{a * 1e9:.0f} ns (the largest document alone) plus b = {b * 1e9:.3f} ns per "
+                      f"document, so {1e9 * (a + b * (w.n_docs - 1)):.0f} ns per lookup over "
+                      f"{w.n_docs} documents; the same model predicts the half block "
+                      f"({half} sub-indexes) {err:+.1%} off its measured time",
+            "block_lookups_per_s_1_thread": l_1 / t_1, "block_lookups_per_s": l_n / t_n,
+            "ns_per_lookup": a * 1e9, "ns_per_lookup_document": b * 1e9,
+            "model_error_half_block": err, "build_s": build_s}
+
+
 def cpu_baseline(w, synth, oracle, qs, budget_s, threads=None):
     """The CPU oracle on bounded samples: the S smallest documents of the
     workload (their own compact plan), for S = 32 and 256, queried with the
     query set (cycled) for half the budget each.  The time per lookup is
     a + b * S (a per lookup: terms, hashing; b per document); the rate is
-    extrapolated to the workload's document count along that line."""
+    extrapolated to the workload's document count along that line.  Used
+    where a whole block is too large to build on the host in the run."""
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
     if w.kind != "dna" or w.n_docs < 256:
@@ -342,8 +438,12 @@ def main():
     rbuf = torch.empty(8 << 30, dtype=torch.uint8, device="cuda")
     cobs.read_bandwidth(rbuf)
     stream_read = max(cobs.read_bandwidth(rbuf) for _ in range(3))
+    # random 1 KiB row reads (the gather's access pattern, cached loads) over
+    # working sets that fit each XCD's L2, the last-level cache, or only HBM
+    rows_read = {label: cobs.read_rows_bandwidth(rbuf[:nb], 24 << 20, cached=True)
+                 for label, nb in (("4MiB", 4 << 20), ("128MiB", 128 << 20), ("8GiB", 8 << 30))}
     del rbuf
-    log(f"read ceiling {stream_read:.0f} GB/s")
+    log(f"read ceiling {stream_read:.0f} GB/s; random rows {rows_read}")
 
     # top-k run of the same set (K = 0, top-100)
     topk_ms = None
@@ -378,11 +478,22 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        cpu = cpu_baseline(w, synth, oracle, qs, args.cpu_seconds)
-        one = cpu_baseline(w, synth, oracle, qs, args.cpu_seconds / 2, threads=1)
-        if cpu and one:
-            cpu["value_1_thread"] = one["value"]
-            cpu["sample_1_thread"] = one["sample"]
+        threads = min(os.cpu_count() or 1, 16)
+        if w.kind == "dna" and w.B == 8192 and args.scale == 1:
+            order, n_terms = ix.order()
+            cpu = cpu_baseline_block(w, synth, oracle, qs, order, n_terms, args.cpu_seconds, threads)
+            log(f"cpu baseline ({threads} threads): {cpu['sample']}")
+        else:
+            cpu = cpu_baseline(w, synth, oracle, qs, args.cpu_seconds, threads)
+            one = cpu_baseline(w, synth, oracle, qs, args.cpu_seconds / 2, threads=1)
+            if cpu and one:
+                cpu["value_1_thread"] = one["value"]
+                cpu["sample_1_thread"] = one["sample"]
+        try:
+            import psutil
+            cpu["host_ram_gb"] = psutil.virtual_memory().total / 1e9
+        except Exception:
+            pass
         log("cpu baseline done")
 
     offload = None
@@ -445,6 +556,7 @@ def main():
         },
         "hbm": {
             "stream_read_GBps": stream_read,
+            "random_rows_GBps": rows_read,
             "gather_frac_of_stream_read": achieved / stream_read,
             "gather_counted_GBps": traffic / (gather_ms * 1e-3) / 1e9 if traffic else None,
         },

@@ -197,8 +197,10 @@ cobs_status cobs_index_info(const cobs_index *ix, cobs_index_info_t *info);
  * each of at most device_budget_bytes / 2 and holding a group of whole
  * consecutive blocks: the copy of one group (DMA over the host link) overlaps
  * the gather of the previous one.  A batch therefore reads the whole matrix
- * once over the host link, and large batches amortise it.  Results are
- * identical.  Batches on an offloaded index run one at a time.
+ * once over the host link, and large batches amortise it.  A batch whose
+ * rows are far fewer than the matrix instead reads each row slice it needs
+ * in place, straight from host memory (cobs_host_reads).  Results are
+ * identical.  Streamed batches on an offloaded index run one at a time.
  * cobs_index_onload moves the matrix back into device memory.  Neither may
  * run while another thread queries the index.
  * Errors: EBUDGET when half the budget cannot hold the largest block;
@@ -337,7 +339,7 @@ cobs_status cobs_query_results(cobs_index *ix, const uint8_t *bytes, const uint6
 /*
  * Query several indexes as one collection (the paper's tool queries several
  * index files, so that a front-end can pick datasets or categories: section
- * 6).  Documents are numbered across the indexes in the given order: input
+ * 4, conclusion and future work).  Documents are numbered across the indexes in the given order: input
  * document d of indexes[j] is n_docs(0) + ... + n_docs(j - 1) + d.  The
  * indexes must share the term definition (kind, q, canonical), so each
  * query has the same l, and the same threshold T, in every one; h, p, seed
@@ -452,19 +454,40 @@ typedef enum {
 } cobs_order;
 
 /*
+ * How a batch on an offloaded index (cobs_index_offload) reads the matrix
+ * in pinned host memory.
+ *  COBS_HOST_READS_STREAM    every group of blocks is copied into a device
+ *                            staging buffer and gathered there: the whole
+ *                            matrix crosses the host link once per batch;
+ *  COBS_HOST_READS_IN_PLACE  the gather reads each row slice it needs
+ *                            straight from host memory (only the rows of the
+ *                            batch's terms cross the link, as random reads);
+ *  COBS_HOST_READS_AUTO      in place when the batch's rows (bounded by its
+ *                            windows: windows x h x row bytes per term) are
+ *                            under half the matrix, else streamed.
+ */
+typedef enum {
+    COBS_HOST_READS_AUTO = 0,
+    COBS_HOST_READS_STREAM = 1,
+    COBS_HOST_READS_IN_PLACE = 2,
+} cobs_host_reads;
+
+/*
  * Launch shape of the gather kernel for an index: `unroll` terms whose rows
  * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4), `chunk`, the
  * most distinct terms per work item (longer queries are split and their
  * counts merged; a batch is split into about two work items per resident
- * wavefront, with items of at most `chunk` terms), and `order` (cobs_order).
- * 0 = defaults (8 or 2; 16384; COBS_ORDER_AUTO).  Results never depend on
- * any of them.
+ * wavefront, with items of at most `chunk` terms), `order` (cobs_order) and
+ * `host_reads` (cobs_host_reads; offloaded indexes only).  0 = defaults (8
+ * or 2; 16384; COBS_ORDER_AUTO; COBS_HOST_READS_AUTO).  Results never depend
+ * on any of them.
  */
 typedef struct {
     uint32_t unroll;
     uint32_t chunk;
     double gather_ms;    /* cobs_tune: the chosen shape's gather time */
     uint32_t order;
+    uint32_t host_reads;
 } cobs_tuning;
 
 /* Time the gather kernel on the sample batch for every supported unroll and
@@ -540,6 +563,22 @@ cobs_status cobs_profile(int enable);
  * multiple of 16.  Errors: EINVAL, EDEVICE.
  */
 cobs_status cobs_read_bandwidth(const void *buf, uint64_t bytes, void *stream, double *gbps);
+
+/*
+ * Read ceiling of random row reads, the access pattern of the gather (section
+ * 2.2: one row of the matrix per query term): about `reads` reads of one
+ * 1 KiB row each (a wavefront's 64 lanes x 16 bytes, eight rows in flight per
+ * wavefront, 8,192 wavefronts), every row drawn uniformly from the
+ * floor(bytes / 1024) rows of [buf, buf + bytes) by a counter-based hash.
+ * cached != 0: ordinary loads, so that a buffer small enough for the L2 or
+ * the last-level cache is read from there; 0: non-temporal loads.  Three
+ * passes on `stream`, the first warming the caches; *gbps = bytes read by
+ * one pass / the faster of the other two (10^9 B/s).  buf: device memory,
+ * 16-byte aligned, only read; bytes: 1 KiB to 2^32 - 1 rows of 1 KiB.
+ * Errors: EINVAL, EDEVICE.
+ */
+cobs_status cobs_read_rows_bandwidth(const void *buf, uint64_t bytes, uint64_t reads, int cached,
+                                     void *stream, double *gbps);
 cobs_status cobs_profile_read(cobs_kernel_timing *gather, int reset);
 
 /* ---- misc --------------------------------------------------------------- */

@@ -23,6 +23,7 @@ DNA, BYTES = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 MODE_BATCHED, MODE_PLAIN = 0, 1
 ORDER_AUTO, ORDER_QUERIES, ORDER_SLICES = 0, 1, 2   # cobs_order: gather work-item order
+HOST_READS_AUTO, HOST_READS_STREAM, HOST_READS_IN_PLACE = 0, 1, 2   # cobs_host_reads
 
 
 class CobsError(RuntimeError):
@@ -75,7 +76,7 @@ class ServeStats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("unroll", C.c_uint32), ("chunk", C.c_uint32), ("gather_ms", C.c_double),
-                ("order", C.c_uint32)]
+                ("order", C.c_uint32), ("host_reads", C.c_uint32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_uint64)
@@ -149,6 +150,8 @@ EXPORTS = {
     "cobs_profile": (C.c_int, [C.c_int]),
     "cobs_read_bandwidth": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p,
                                       C.POINTER(C.c_double)]),
+    "cobs_read_rows_bandwidth": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_int,
+                                           C.c_void_p, C.POINTER(C.c_double)]),
     "cobs_profile_read": (C.c_int, [C.POINTER(KernelTiming), C.c_int]),
     "cobs_last_error": (C.c_char_p, []),
     "cobs_now_ns": (C.c_uint64, []),
@@ -368,8 +371,8 @@ class Index:
                                C.byref(t)))
         return dict(unroll=t.unroll, chunk=t.chunk, order=t.order, gather_ms=t.gather_ms)
 
-    def set_tuning(self, unroll=0, chunk=0, order=ORDER_AUTO) -> None:
-        t = Tuning(unroll, chunk, 0.0, order)
+    def set_tuning(self, unroll=0, chunk=0, order=ORDER_AUTO, host_reads=HOST_READS_AUTO) -> None:
+        t = Tuning(unroll, chunk, 0.0, order, host_reads)
         _check(lib().cobs_set_tuning(self._h, C.byref(t)))
 
     def query_flat(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,
@@ -578,6 +581,17 @@ def read_bandwidth(tensor, stream=None) -> float:
     nbytes = tensor.numel() * tensor.element_size() // 16 * 16
     _check(lib().cobs_read_bandwidth(C.c_void_p(tensor.data_ptr()), nbytes, _stream(stream),
                                      C.byref(gbps)))
+    return gbps.value
+
+
+def read_rows_bandwidth(tensor, reads: int, cached: bool = True, stream=None) -> float:
+    """GB/s of random 1 KiB row reads over a device tensor
+    (cobs_read_rows_bandwidth): cached loads over a buffer that fits in the
+    caches measure the cache-resident ceiling."""
+    gbps = C.c_double()
+    nbytes = tensor.numel() * tensor.element_size()
+    _check(lib().cobs_read_rows_bandwidth(C.c_void_p(tensor.data_ptr()), nbytes, int(reads),
+                                          1 if cached else 0, _stream(stream), C.byref(gbps)))
     return gbps.value
 
 

@@ -16,7 +16,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I", os.path.join(PKG, "..", "include")]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HOST_SOURCES = ["lib.cpp", "query.cpp", "index_ops.cpp", "serve.cpp", "docset.cpp"]
-DEVICE_SOURCES = ["kernels.hip"]
+DEVICE_SOURCES = ["kernels.hip", "gather.hip"]
 
 
 def build(verbose: bool = False) -> str:

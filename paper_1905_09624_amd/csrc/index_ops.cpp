@@ -78,10 +78,15 @@ cobs_status cobs_index_offload(cobs_index *ix, uint64_t device_budget_bytes)
     uint64_t stage = 0;
     cobs_status s = plan_groups(ix, device_budget_bytes, groups, stage);
     if (s != COBS_OK) return s;
-    hipError_t e = hipHostMalloc((void **)&ix->h_matrix, std::max<uint64_t>(ix->total_bytes, 1));
+    hipError_t e = hipHostMalloc((void **)&ix->h_matrix, std::max<uint64_t>(ix->total_bytes, 1),
+                                 hipHostMallocMapped);
     if (e != hipSuccess) {
         ix->h_matrix = nullptr;
         return set_error(COBS_ENOMEM, "pinned host memory for the matrix");
+    }
+    if ((e = hipHostGetDevicePointer((void **)&ix->h_dev_matrix, ix->h_matrix, 0)) != hipSuccess) {
+        ix->release_offload();
+        return hip_error(e, "hipHostGetDevicePointer(matrix)");
     }
     if (ix->total_bytes &&
         (e = hipMemcpy(ix->h_matrix, ix->d_matrix, ix->total_bytes, hipMemcpyDeviceToHost)) != hipSuccess) {
@@ -255,10 +260,12 @@ cobs_status cobs_index_load(const char *path, int device, uint64_t device_budget
         std::vector<cobs_index::Group> groups;
         uint64_t stage = 0;
         if ((s = plan_groups(ix.get(), device_budget_bytes, groups, stage)) != COBS_OK) return s;
-        if (hipHostMalloc((void **)&ix->h_matrix, std::max<uint64_t>(T, 1)) != hipSuccess) {
+        if (hipHostMalloc((void **)&ix->h_matrix, std::max<uint64_t>(T, 1), hipHostMallocMapped) != hipSuccess) {
             ix->h_matrix = nullptr;
             return set_error(COBS_ENOMEM, "pinned host memory for the matrix");
         }
+        if (hipHostGetDevicePointer((void **)&ix->h_dev_matrix, ix->h_matrix, 0) != hipSuccess)
+            return set_error(COBS_EDEVICE, "hipHostGetDevicePointer(matrix)");
         if (T && std::fread(ix->h_matrix, 1, T, in.f) != T) return bad("truncated matrix");
         if ((s = setup_staging(ix.get(), groups, stage)) != COBS_OK) return s;
     } else {

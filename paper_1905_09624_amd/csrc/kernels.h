@@ -178,6 +178,11 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st);
 constexpr uint32_t kReadGrid = 2048;
 constexpr uint64_t kReadChunk = 4096;
 hipError_t launch_read(const void *p, uint64_t bytes, int pattern, uint32_t *sink, hipStream_t st);
+// Random row reads: each of the kReadGrid * 4 wavefronts reads per_wave
+// (a multiple of 8) rows of kSliceBytes drawn from the bytes / kSliceBytes
+// rows at p (rows < 2^32), with ordinary (cached) or non-temporal loads.
+hipError_t launch_read_rows(const void *p, uint64_t bytes, uint64_t per_wave, bool cached,
+                            uint64_t seed, uint32_t *sink, hipStream_t st);
 
 // Classic merge: every row of out (out_stride bytes) = the na document bits
 // of a's row, then b's row bits; strides are multiples of 4.

@@ -215,6 +215,7 @@ void cobs_index::release_offload()
     copy_stream = nullptr;
     d_group_slices = nullptr;
     h_matrix = nullptr;
+    h_dev_matrix = nullptr;
     groups.clear();
     stage_bytes = 0;
 }

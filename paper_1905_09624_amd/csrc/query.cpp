@@ -87,6 +87,174 @@ uint32_t default_order(const cobs_index *ix)
     return biggest <= kSliceMajorBytes ? COBS_ORDER_SLICES : COBS_ORDER_QUERIES;
 }
 
+// Host plan of one query batch: windows per query, dedup work lists, launch
+// shape and score-buffer slots, and the layout of the metadata uploaded for
+// the kernels.
+struct BatchPlan {
+    uint32_t n = 0;
+    uint64_t byte0 = 0, nbytes = 0, W = 0, maxw = 0, tslots = 0, groups = 0, pslots = 0;
+    std::vector<uint64_t> hv;            // qstart[n] | wbase[n + 1]
+    std::vector<uint64_t> tb;            // first global dedup slot of each query
+    std::vector<uint32_t> lds_q;         // LDS-table queries: n_small small ones, then large ones
+    std::vector<uint32_t> g_q, gprefix;  // global-table queries; first workgroup of each, then the total
+    uint32_t n_small = 0, n_large = 0;
+    int planes = 0, unroll = 0, grid = 0;
+    bool packed = false;
+    bool in_place = false;               // offloaded index: rows read from host memory in place
+    uint32_t chunk = 0;
+    size_t o_wb = 0, o_tb = 0, o_sl = 0, o_lq = 0, o_gq = 0, o_gp = 0, meta = 0;
+};
+
+cobs_status plan_batch(cobs_index *ix, const BatchSpec &b, BatchPlan &pl)
+{
+    const uint32_t n = b.n;
+    pl.n = n;
+    if (!b.q_off) return set_error(COBS_EINVAL, "q_off is NULL");
+    if (b.k_den == 0) return set_error(COBS_EINVAL, "k_den must be > 0");
+    if (b.score_bits != 16 && b.score_bits != 32)
+        return set_error(COBS_EINVAL, "score_bits must be 16 or 32");
+    if (b.mem != COBS_MEM_HOST && b.mem != COBS_MEM_DEVICE)
+        return set_error(COBS_EINVAL, "mem must be COBS_MEM_HOST or COBS_MEM_DEVICE");
+    const uint32_t q = ix->prm.q, h = ix->prm.num_hashes;
+    const uint32_t n_slices = (uint32_t)ix->slices.size();
+    pl.byte0 = b.q_off[0];
+    for (uint32_t i = 0; i < n; ++i)
+        if (b.q_off[i + 1] < b.q_off[i]) return set_error(COBS_EINVAL, "q_off must be non-decreasing");
+    pl.nbytes = b.q_off[n] - b.q_off[0];
+    if (pl.nbytes && !b.bytes) return set_error(COBS_EINVAL, "bytes is NULL");
+
+    pl.hv.assign(2 * (size_t)n + 1, 0);
+    uint64_t *qstart = pl.hv.data(), *wbase = pl.hv.data() + n;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t len = b.q_off[i + 1] - b.q_off[i];
+        const uint64_t nw = len >= q ? len - q + 1 : 0;
+        qstart[i] = b.q_off[i] - pl.byte0;
+        wbase[i] = pl.W;
+        pl.W += nw;
+        pl.maxw = std::max(pl.maxw, nw);
+    }
+    wbase[n] = pl.W;
+    // dedup work lists: queries with an LDS set; queries with a global table
+    // and the first workgroup of each
+    pl.tb.assign(n, 0);
+    std::vector<uint32_t> lds_large;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t nw = wbase[i + 1] - wbase[i];
+        const uint64_t slots = dedup_table_slots(nw);
+        pl.tb[i] = pl.tslots;
+        pl.tslots += slots;
+        if (slots) {
+            pl.g_q.push_back(i);
+            pl.gprefix.push_back((uint32_t)pl.groups);
+            pl.groups += dedup_groups(nw);
+        } else if (dedup_small_table(nw)) {
+            pl.lds_q.push_back(i);
+        } else {
+            lds_large.push_back(i);
+        }
+    }
+    pl.n_small = (uint32_t)pl.lds_q.size();
+    pl.n_large = (uint32_t)lds_large.size();
+    pl.lds_q.insert(pl.lds_q.end(), lds_large.begin(), lds_large.end());
+    if (pl.groups > 0x7FFFFFFFull) return set_error(COBS_EINVAL, "query batch too large");
+    pl.gprefix.push_back((uint32_t)pl.groups);
+
+    // An offloaded index is read in place (each row slice straight from
+    // pinned host memory over the host link) when the batch's rows are far
+    // fewer than the matrix, else streamed group by group through device
+    // staging buffers.  Random row reads over the link run at about half the
+    // rate of whole-group copies, so in place pays below half the matrix;
+    // the bound uses windows, which bound the distinct terms.
+    if (ix->h_matrix) {
+        uint64_t per_term = 0;
+        for (const SliceDesc &sd : ix->slices) per_term += sd.width;
+        const uint64_t rows_bytes = pl.W * h * per_term;
+        const uint32_t mode = b.host_reads ? b.host_reads : ix->tuned_host_reads;
+        pl.in_place = mode == COBS_HOST_READS_IN_PLACE ||
+                      (mode == COBS_HOST_READS_AUTO && 2 * rows_bytes < ix->total_bytes);
+    }
+    pl.planes = gather_planes_for(pl.maxw);
+    int unroll = b.unroll ? (int)b.unroll : (ix->tuned_unroll ? ix->tuned_unroll : gather_default_unroll((int)h));
+    if (!gather_unroll_valid(unroll, (int)h)) unroll = gather_default_unroll((int)h);
+    pl.unroll = unroll;
+    // An index whose slices are all narrow (blocks of at most 4,096
+    // documents) is gathered by the packed kernel, several terms per load;
+    // where wide slices carry most of the bytes, the narrow ones ride along
+    // in the same launch (a separate packed launch measured slower there).
+    // An offloaded index streams through the plain kernel (group-rebased
+    // slices); read in place it takes the same kernels as in HBM.
+    pl.packed = ix->packed && (!ix->h_matrix || pl.in_place);
+    int grid = gather_grid(pl.planes, unroll, (int)h, pl.packed);
+    const uint32_t cap = b.chunk_cap ? b.chunk_cap : (ix->tuned_chunk ? ix->tuned_chunk : kDefaultChunkCap);
+    pl.chunk = b.chunk ? b.chunk : auto_chunk(pl.W, n_slices, grid, cap);
+    uint64_t items = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t nw = wbase[i + 1] - wbase[i];
+        if (nw > pl.chunk) pl.pslots += 1;   // may be split: one score buffer
+        items += (nw + pl.chunk - 1) / pl.chunk;
+    }
+    // no more wavefronts than work items (4 per workgroup)
+    items *= n_slices;
+    if ((uint64_t)grid * 4 > items) grid = (int)std::max<uint64_t>(1, (items + 3) / 4);
+    pl.grid = grid;
+
+    // metadata: qstart | wbase | tbase | slot | lds_q | g_q | gprefix
+    pl.o_wb = (size_t)n * 8;
+    pl.o_tb = pl.o_wb + (size_t)(n + 1) * 8;
+    pl.o_sl = pl.o_tb + (size_t)n * 8;
+    pl.o_lq = pl.o_sl + (size_t)n * 4;
+    pl.o_gq = pl.o_lq + pl.lds_q.size() * 4;
+    pl.o_gp = pl.o_gq + pl.g_q.size() * 4;
+    pl.meta = batch_meta_bytes(n);
+    return COBS_OK;
+}
+
+// The plan's metadata in its upload layout (pl.meta bytes at dst).
+void write_meta(const BatchPlan &pl, const uint32_t *slots, uint8_t *dst)
+{
+    const size_t n = pl.n;
+    std::memcpy(dst, pl.hv.data(), n * 8);
+    std::memcpy(dst + pl.o_wb, pl.hv.data() + n, (n + 1) * 8);
+    std::memcpy(dst + pl.o_tb, pl.tb.data(), n * 8);
+    if (slots) std::memcpy(dst + pl.o_sl, slots, n * 4);
+    std::memcpy(dst + pl.o_lq, pl.lds_q.data(), pl.lds_q.size() * 4);
+    std::memcpy(dst + pl.o_gq, pl.g_q.data(), pl.g_q.size() * 4);
+    std::memcpy(dst + pl.o_gp, pl.gprefix.data(), pl.gprefix.size() * 4);
+}
+
+// Device addresses of the metadata uploaded to base.
+struct MetaPtrs {
+    const uint64_t *qstart, *wbase, *tbase;
+    const uint32_t *slot, *lds_q, *g_q, *gprefix;
+};
+
+MetaPtrs meta_ptrs(const BatchPlan &pl, const uint8_t *base, bool slots)
+{
+    MetaPtrs m;
+    m.qstart = (const uint64_t *)base;
+    m.wbase = (const uint64_t *)(base + pl.o_wb);
+    m.tbase = (const uint64_t *)(base + pl.o_tb);
+    m.slot = slots ? (const uint32_t *)(base + pl.o_sl) : nullptr;
+    m.lds_q = (const uint32_t *)(base + pl.o_lq);
+    m.g_q = (const uint32_t *)(base + pl.o_gq);
+    m.gprefix = (const uint32_t *)(base + pl.o_gp);
+    return m;
+}
+
+// a1-a3: terms of every window, then each query's distinct terms and their
+// hashes; nterms[i] = l of query i.
+hipError_t launch_front(const cobs_index *ix, const BatchPlan &pl, const MetaPtrs &mp,
+                        const uint8_t *dbytes, uint64_t *terms, uint64_t *table, uint64_t *uterms,
+                        uint64_t *hashes, uint32_t *nterms, hipStream_t st)
+{
+    const TermSpec ts = term_spec(ix->prm);
+    hipError_t e = launch_extract(dbytes, mp.qstart, mp.wbase, pl.n, pl.W, ts, terms, nterms, st);
+    if (e != hipSuccess) return e;
+    return launch_dedup(terms, mp.wbase, mp.tbase, mp.lds_q, pl.n_small, pl.n_large, mp.g_q,
+                        mp.gprefix, (uint32_t)pl.g_q.size(), (uint32_t)pl.groups, table, pl.tslots,
+                        uterms, hashes, nterms, ts, ix->seeds, st);
+}
+
 }  // namespace
 
 // The gather of an offloaded index: group by group, the copy of group g + 2
@@ -137,109 +305,33 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
                       BatchOut &out)
 {
     std::unique_lock<std::mutex> streaming(ix->stream_mu, std::defer_lock);
-    if (ix->h_matrix) streaming.lock();   // one streamed batch at a time
     const uint32_t n = b.n;
     out.num_terms.assign(n, 0);
     out.n.assign(n, 0);
     out.start.assign(n + 1, 0);
     if (n == 0) return COBS_OK;
-    if (!b.q_off) return set_error(COBS_EINVAL, "q_off is NULL");
-    if (b.k_den == 0) return set_error(COBS_EINVAL, "k_den must be > 0");
-    if (b.score_bits != 16 && b.score_bits != 32)
-        return set_error(COBS_EINVAL, "score_bits must be 16 or 32");
-    if (b.mem != COBS_MEM_HOST && b.mem != COBS_MEM_DEVICE)
-        return set_error(COBS_EINVAL, "mem must be COBS_MEM_HOST or COBS_MEM_DEVICE");
-    const uint32_t q = ix->prm.q, h = ix->prm.num_hashes;
+    const uint32_t h = ix->prm.num_hashes;
     const uint32_t n_slices = (uint32_t)ix->slices.size();
-    const uint64_t byte0 = b.q_off[0];
-    const uint64_t nbytes = b.q_off[n] - b.q_off[0];
-    if (nbytes && !b.bytes) return set_error(COBS_EINVAL, "bytes is NULL");
+    BatchPlan pl;
+    {
+        cobs_status ps = plan_batch(ix, b, pl);
+        if (ps != COBS_OK) return ps;
+    }
+    if (ix->h_matrix && !pl.in_place) streaming.lock();   // one streamed batch at a time
+    const uint64_t W = pl.W, tslots = pl.tslots, nbytes = pl.nbytes, byte0 = pl.byte0;
+    const int planes = pl.planes, unroll = pl.unroll, grid = pl.grid;
+    const bool packed = pl.packed;
+    const uint32_t C = pl.chunk;
+    const uint64_t pslots = pl.pslots;
 
-    // host plan: windows, dedup tables, launch shape, score-buffer slots
-    std::vector<uint64_t> hv(2 * (size_t)n + 1);
-    uint64_t *qstart = hv.data(), *wbase = hv.data() + n;
-    uint64_t W = 0, maxw = 0, tslots = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        if (b.q_off[i + 1] < b.q_off[i]) return set_error(COBS_EINVAL, "q_off must be non-decreasing");
-        const uint64_t len = b.q_off[i + 1] - b.q_off[i];
-        const uint64_t nw = len >= q ? len - q + 1 : 0;
-        qstart[i] = b.q_off[i] - byte0;
-        wbase[i] = W;
-        W += nw;
-        maxw = std::max(maxw, nw);
-    }
-    wbase[n] = W;
-    // dedup work lists: queries with an LDS set; queries with a global table
-    // and the first workgroup of each
-    std::vector<uint64_t> tb(n, 0);
-    std::vector<uint32_t> lds_q, lds_large, g_q, gprefix;
-    uint64_t groups = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        const uint64_t nw = wbase[i + 1] - wbase[i];
-        const uint64_t slots = dedup_table_slots(nw);
-        tb[i] = tslots;
-        tslots += slots;
-        if (slots) {
-            g_q.push_back(i);
-            gprefix.push_back((uint32_t)groups);
-            groups += dedup_groups(nw);
-        } else if (dedup_small_table(nw)) {
-            lds_q.push_back(i);
-        } else {
-            lds_large.push_back(i);
-        }
-    }
-    const uint32_t n_small = (uint32_t)lds_q.size();
-    lds_q.insert(lds_q.end(), lds_large.begin(), lds_large.end());
-    if (groups > 0x7FFFFFFFull) return set_error(COBS_EINVAL, "query batch too large");
-    gprefix.push_back((uint32_t)groups);
-    const int planes = gather_planes_for(maxw);
-    int unroll = b.unroll ? (int)b.unroll : (ix->tuned_unroll ? ix->tuned_unroll : gather_default_unroll((int)h));
-    if (!gather_unroll_valid(unroll, (int)h)) unroll = gather_default_unroll((int)h);
-    // An index whose slices are all narrow (blocks of at most 4,096
-    // documents) is gathered by the packed kernel, several terms per load;
-    // where wide slices carry most of the bytes, the narrow ones ride along
-    // in the same launch (a separate packed launch measured slower there).
-    // An offloaded index streams through the plain kernel.
-    const bool packed = ix->packed && !ix->h_matrix;
-    int grid = gather_grid(planes, unroll, (int)h, packed);
-    const uint32_t cap = b.chunk_cap ? b.chunk_cap : (ix->tuned_chunk ? ix->tuned_chunk : kDefaultChunkCap);
-    const uint32_t C = b.chunk ? b.chunk : auto_chunk(W, n_slices, grid, cap);
-    uint64_t pslots = 0, items = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        const uint64_t nw = wbase[i + 1] - wbase[i];
-        if (nw > C) pslots += 1;   // may be split: one score buffer
-        items += (nw + C - 1) / C;
-    }
-    // no more wavefronts than work items (4 per workgroup)
-    items *= n_slices;
-    if ((uint64_t)grid * 4 > items) grid = (int)std::max<uint64_t>(1, (items + 3) / 4);
-    const TermSpec ts = term_spec(ix->prm);
-
-    // uploads
-    // staging: qstart | wbase | tbase | slot | lds_q | g_q | gprefix | query bytes (host mode)
-    const size_t o_wb = (size_t)n * 8, o_tb = o_wb + (size_t)(n + 1) * 8, o_sl = o_tb + (size_t)n * 8;
-    const size_t o_lq = o_sl + (size_t)n * 4, o_gq = o_lq + lds_q.size() * 4;
-    const size_t o_gp = o_gq + g_q.size() * 4;
-    const size_t meta = batch_meta_bytes(n);
+    // uploads: the plan's metadata, then the query bytes (host mode) in one copy
+    const size_t meta = pl.meta;
     COBS_HIP(ws.h_stage.ensure(meta + (b.mem == COBS_MEM_HOST ? nbytes : 0)));
     uint8_t *stg = ws.h_stage.as<uint8_t>();
-    std::memcpy(stg, qstart, (size_t)n * 8);
-    std::memcpy(stg + o_wb, wbase, (size_t)(n + 1) * 8);
-    std::memcpy(stg + o_tb, tb.data(), (size_t)n * 8);
-    if (b.slots) std::memcpy(stg + o_sl, b.slots, (size_t)n * 4);
-    std::memcpy(stg + o_lq, lds_q.data(), lds_q.size() * 4);
-    std::memcpy(stg + o_gq, g_q.data(), g_q.size() * 4);
-    std::memcpy(stg + o_gp, gprefix.data(), gprefix.size() * 4);
+    write_meta(pl, b.slots, stg);
     COBS_HIP(ws.meta.ensure(meta));
     COBS_HIP(hipMemcpyAsync(ws.meta.p, stg, meta, hipMemcpyHostToDevice, st));
-    const uint64_t *d_qstart = ws.meta.as<uint64_t>();
-    const uint64_t *d_wbase = (const uint64_t *)(ws.meta.as<uint8_t>() + o_wb);
-    const uint64_t *d_tbase = (const uint64_t *)(ws.meta.as<uint8_t>() + o_tb);
-    const uint32_t *d_slot = b.slots ? (const uint32_t *)(ws.meta.as<uint8_t>() + o_sl) : nullptr;
-    const uint32_t *d_lds_q = (const uint32_t *)(ws.meta.as<uint8_t>() + o_lq);
-    const uint32_t *d_g_q = (const uint32_t *)(ws.meta.as<uint8_t>() + o_gq);
-    const uint32_t *d_gprefix = (const uint32_t *)(ws.meta.as<uint8_t>() + o_gp);
+    const MetaPtrs mp = meta_ptrs(pl, ws.meta.as<uint8_t>(), b.slots != nullptr);
     // the query bytes in the workspace (256-byte aligned, 64 bytes of slack:
     // the extract kernel reads whole aligned dwords around each window)
     COBS_HIP(ws.bytes.ensure(nbytes + 64));
@@ -263,13 +355,8 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     uint32_t *d_out_n = d_nterms + n;
     uint32_t *d_out_start = d_out_n + n;
     COBS_HIP(ws.table.ensure(std::max<uint64_t>(tslots, 1) * 8));
-    COBS_HIP(launch_extract(dbytes, d_qstart, d_wbase, n, W, ts, ws.terms.as<uint64_t>(), d_nterms,
-                            st));
-    COBS_HIP(launch_dedup(ws.terms.as<uint64_t>(), d_wbase, d_tbase, d_lds_q, n_small,
-                          (uint32_t)lds_large.size(), d_g_q, d_gprefix, (uint32_t)g_q.size(),
-                          (uint32_t)groups, ws.table.as<uint64_t>(), tslots,
-                          ws.uterms.as<uint64_t>(), ws.hashes.as<uint64_t>(), d_nterms, ts,
-                          ix->seeds, st));
+    COBS_HIP(launch_front(ix, pl, mp, dbytes, ws.terms.as<uint64_t>(), ws.table.as<uint64_t>(),
+                          ws.uterms.as<uint64_t>(), ws.hashes.as<uint64_t>(), d_nterms, st));
     if (b.terms_out) {
         std::vector<uint32_t> nt(n);
         COBS_HIP(hipMemcpyAsync(nt.data(), d_nterms, (size_t)n * 4, hipMemcpyDeviceToHost, st));
@@ -307,7 +394,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     for (int attempt = 0;; ++attempt) {
         COBS_HIP(ws.cand_key.ensure(ws.cand_cap * 8));
         COBS_HIP(ws.cand_q.ensure(ws.cand_cap * 4));
-        COBS_HIP(launch_plan(d_nterms, d_wbase, d_slot, n, C, n_slices,
+        COBS_HIP(launch_plan(d_nterms, mp.wbase, mp.slot, n, C, n_slices,
                              b.k_num, b.k_den, ell_limit, ws.qinfo.as<QInfo>(),
                              ws.qorder.as<uint32_t>(), ws.chunk_prefix.as<uint32_t>(),
                              &dsc->total_items, &dsc->work_counter, &dsc->cand_counter,
@@ -349,8 +436,10 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
                 if (!e) COBS_HIP(hipEventCreate(&e));
             COBS_HIP(hipEventRecord(ws.ev[0], st));
         }
-        if (n_slices && !ix->h_matrix) COBS_HIP(launch_gather(ga, planes, unroll, grid, packed, st));
-        if (n_slices && ix->h_matrix) {
+        if (pl.in_place) ga.matrix = ix->h_dev_matrix;
+        if (n_slices && (!ix->h_matrix || pl.in_place))
+            COBS_HIP(launch_gather(ga, planes, unroll, grid, packed, st));
+        if (n_slices && ix->h_matrix && !pl.in_place) {
             cobs_status gs = gather_streamed(ix, ws, ga, planes, unroll, grid, st);
             if (gs != COBS_OK) return gs;
         }
@@ -730,9 +819,11 @@ cobs_status cobs_set_tuning(cobs_index *ix, const cobs_tuning *t)
     if (t->unroll && !gather_unroll_valid((int)t->unroll, (int)ix->prm.num_hashes))
         return set_error(COBS_EINVAL, "unsupported unroll for this index");
     if (t->order > COBS_ORDER_SLICES) return set_error(COBS_EINVAL, "unknown work-item order");
+    if (t->host_reads > COBS_HOST_READS_IN_PLACE) return set_error(COBS_EINVAL, "unknown host_reads");
     ix->tuned_unroll = (int)t->unroll;
     ix->tuned_chunk = t->chunk;
     ix->tuned_order = t->order;
+    ix->tuned_host_reads = t->host_reads;
     return COBS_OK;
 }
 
@@ -745,7 +836,7 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
     const uint32_t chunks[] = {0, 512, 1024, 2048, 4096, 8192, 16384, 1u << 20};
     Workspace *ws = acquire_workspace(ix);
     const uint32_t order0 = default_order(ix);
-    cobs_tuning win{0, 0, 1e300, order0};
+    cobs_tuning win{0, 0, 1e300, order0, ix->tuned_host_reads};
     cobs_status s = COBS_OK;
     auto time_shape = [&](int u, uint32_t c, uint32_t order) -> double {
         BatchSpec spec;
@@ -773,14 +864,15 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
         for (uint32_t c : chunks) {
             const double t = time_shape(u, c, order0);
             if (s != COBS_OK) break;
-            if (t < win.gather_ms) win = cobs_tuning{(uint32_t)u, c, t, order0};
+            if (t < win.gather_ms) win = cobs_tuning{(uint32_t)u, c, t, order0, ix->tuned_host_reads};
         }
         if (s != COBS_OK) break;
     }
     if (s == COBS_OK) {
         const uint32_t other = order0 == COBS_ORDER_SLICES ? COBS_ORDER_QUERIES : COBS_ORDER_SLICES;
         const double t = time_shape((int)win.unroll, win.chunk, other);
-        if (s == COBS_OK && t < win.gather_ms) win = cobs_tuning{win.unroll, win.chunk, t, other};
+        if (s == COBS_OK && t < win.gather_ms)
+            win = cobs_tuning{win.unroll, win.chunk, t, other, ix->tuned_host_reads};
     }
     release_workspace(ix, ws);
     if (s != COBS_OK) return s;
@@ -818,6 +910,43 @@ cobs_status cobs_read_bandwidth(const void *buf, uint64_t bytes, void *stream, d
         if (e) (void)hipEventDestroy(e);
     if (s != COBS_OK) return s;
     *gbps = best > 0.f ? (double)bytes / (best * 1e-3) / 1e9 : 0.0;
+    return COBS_OK;
+}
+
+cobs_status cobs_read_rows_bandwidth(const void *buf, uint64_t bytes, uint64_t reads, int cached,
+                                     void *stream, double *gbps)
+{
+    if (!buf || !gbps) return set_error(COBS_EINVAL, "NULL argument");
+    if (((uintptr_t)buf & 15u) || bytes < kSliceBytes || bytes / kSliceBytes > 0xFFFFFFFFull)
+        return set_error(COBS_EINVAL, "buffer must be 16-byte aligned and hold 1 to 2^32 - 1 rows of 1 KiB");
+    if (reads == 0) return set_error(COBS_EINVAL, "reads must be positive");
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t waves = (uint64_t)kReadGrid * 4;
+    const uint64_t per_wave = ((reads + waves - 1) / waves + 7) / 8 * 8;
+    DevBuf sink;
+    COBS_HIP(sink.ensure((size_t)kReadGrid * 4));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    cobs_status s = COBS_OK;
+    for (hipEvent_t &e : ev)
+        if (s == COBS_OK && hipEventCreate(&e) != hipSuccess) s = set_error(COBS_EDEVICE, "hipEventCreate");
+    // the first pass warms the caches; the faster of the next two counts
+    float best = 0.f;
+    for (int pass = 0; pass < 3 && s == COBS_OK; ++pass) {
+        float ms = 0.f;
+        hipError_t e = hipEventRecord(ev[0], st);
+        if (e == hipSuccess)
+            e = launch_read_rows(buf, bytes, per_wave, cached != 0, 0x9E3779B97F4A7C15ull * (pass + 1),
+                                 sink.as<uint32_t>(), st);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) s = hip_error(e, "row read pass");
+        else if (pass > 0 && ms > 0.f && (best == 0.f || ms < best)) best = ms;
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s != COBS_OK) return s;
+    *gbps = best > 0.f ? (double)(per_wave * waves * kSliceBytes) / (best * 1e-3) / 1e9 : 0.0;
     return COBS_OK;
 }
 

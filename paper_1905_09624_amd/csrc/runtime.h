@@ -97,6 +97,7 @@ struct BatchSpec {
     uint32_t chunk_cap = 0;            // automatic chunk's maximum; 0 = tuned or kDefaultChunkCap
     uint32_t unroll = 0;               // terms in flight per wavefront; 0 = tuned or default
     uint32_t order = 0;                // cobs_order of the work items; 0 = tuned or by slice size
+    uint32_t host_reads = 0;           // cobs_host_reads (offloaded index); 0 = tuned or automatic
     uint32_t *full_scores = nullptr;   // host [n * n_docs]: full score mode
     uint64_t *terms_out = nullptr;     // host [windows]: terms-only mode
     const uint32_t *slots = nullptr;   // host [n]: score-buffer slot of each query in accum
@@ -137,6 +138,8 @@ struct cobs_index {
         uint64_t off, bytes;         // byte range of the matrix
     };
     uint8_t *h_matrix = nullptr;
+    uint8_t *h_dev_matrix = nullptr;   // device address of h_matrix (rows read in place)
+    uint32_t tuned_host_reads = 0;     // cobs_tuning.host_reads
     std::vector<Group> groups;
     cobs::SliceDesc *d_group_slices = nullptr;   // slices, base relative to their group
     uint8_t *d_stage[2] = {nullptr, nullptr};

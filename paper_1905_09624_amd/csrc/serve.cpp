@@ -89,11 +89,11 @@ void cobs_server::worker(int lane)
         batch.clear();
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] { return stopping || !ready.empty(); });
-            if (ready.empty()) {
-                if (stopping && waiting.empty()) return;
-                continue;
-            }
+            // while stopping, requests still waiting for a score buffer are
+            // admitted when a batch in flight frees one (its worker then
+            // notifies): sleep until then instead of polling
+            cv_work.wait(lk, [&] { return !ready.empty() || (stopping && waiting.empty()); });
+            if (ready.empty()) return;
             const Request &head = *ready.front();
             const uint32_t kn = head.k_num, kd = head.k_den, tk = head.topk;
             uint64_t windows = 0;

@@ -240,7 +240,7 @@ def test_bench_reads_traffic_only_for_the_current_kernel(tmp_path, monkeypatch):
     assert bench.committed_traffic("text-50k") is None          # another workload
     t = bench.committed_traffic("compact-100k")
     assert t is None or t > 266_739_329_024                     # at least the rows it must read
-    changed = tmp_path / "kernels.hip"
+    changed = tmp_path / "gather.hip"
     changed.write_bytes(open(bench.KERNEL_SOURCE, "rb").read() + b"\n")
     monkeypatch.setattr(bench, "KERNEL_SOURCE", str(changed))
     assert bench.committed_traffic("compact-100k") is None

@@ -123,3 +123,56 @@ def test_collection_without_terms(B):
     for x, (q0, q1) in zip(gix.query(data, off, k=(0, 1)), ((0, 80), (80, 112))):
         ids, sc, l = oix.query(data[q0:q1].tobytes(), 0, 1, 0)
         assert x[2] == l and np.array_equal(x[0], ids) and np.array_equal(x[1], sc)
+
+
+def _wide_cases():
+    # (kind, q, canonical, h, p, B, documents): blocks wider than 4,096
+    # documents, so the gather runs its unpacked instantiations (one term per
+    # 1 KiB load, h rows ANDed per term) for every h from 2 to 8
+    return [(0, 31, True, 2, 0.3, 0, 4600), (1, 8, False, 3, 0.1, 8192, 9000),
+            (0, 21, False, 4, 0.2, 0, 5000), (1, 5, False, 5, 0.05, 0, 4200),
+            (0, 31, True, 6, 0.3, 5000, 9100), (1, 8, False, 7, 0.5, 0, 4400),
+            (0, 15, True, 8, 0.01, 8192, 8500)]
+
+
+@pytest.mark.parametrize("case", _wide_cases(), ids=lambda c: f"{'bytes' if c[0] else 'dna'}-h{c[3]}-B{c[5]}-D{c[6]}")
+def test_wide_blocks_every_h_match_oracle(case):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_09624_amd as cobs
+    kind, q, canonical, h, p, B, n_docs = case
+    rng = np.random.default_rng(7000 + 10 * h + kind)
+    docs = [[_string(rng, kind, int(rng.integers(q, q + 150)))] for _ in range(n_docs)]
+    d = oracle.Docs.from_lists(docs)
+    seed = 0xB10C + h
+    prm = cobs.make_params(kind, q, canonical, h, p, B, seed)
+    gix = cobs.Index.build(prm, d.bytes, d.str_off, d.doc_str)
+    oix = oracle.OracleIndex(d, kind=kind, q=q, canonical=canonical, h=h, p=p, B=B, seed=seed)
+    # a slice wider than 512 bytes: the index is gathered one term per load
+    info = gix.info()
+    assert max(gix.block(b)["stride"] for b in range(info["n_blocks"])) > 512
+    # queries: planted substrings, random strings, and one long enough to be
+    # split into several work items
+    qs = [b"", _string(rng, kind, 4000)]
+    for j in range(24):
+        s = docs[int(rng.integers(0, n_docs))][0]
+        a = int(rng.integers(0, len(s) - q + 1))
+        qs.append(s[a:])
+        qs.append(_string(rng, kind, int(rng.integers(q, 200))))
+    off = np.zeros(len(qs) + 1, np.uint64)
+    np.cumsum([len(x) for x in qs], out=off[1:])
+    data = np.frombuffer(b"".join(qs), np.uint8)
+    want = [oix.query_scores(x) for x in qs]
+    for unroll in (2, 4):
+        gix.set_tuning(unroll, 0)
+        sc, nt = gix.scores(data, off)
+        for j in range(len(qs)):
+            assert nt[j] == want[j][1] and np.array_equal(sc[j], want[j][0]), (unroll, j)
+        for k, topk, mode in (((4, 5), 0, 0), ((1, 2), 0, 1), ((0, 1), 5, 0)):
+            got = gix.query(data, off, k=k, topk=topk, mode=mode)
+            for j, x in enumerate(qs):
+                ids, scores, l = oix.query(x, k[0], k[1], topk)
+                assert got[j][2] == l and np.array_equal(got[j][0], ids), (unroll, j, k)
+                assert np.array_equal(got[j][1], scores), (unroll, j, k)
+    gix.set_tuning(0, 0)
