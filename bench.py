@@ -126,7 +126,8 @@ def committed_traffic(workload: str):
         return None
 
 
-def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, plain_n, streams):
+def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, plain_n, streams,
+                  set_launch=None):
     """Served latency and throughput on the resident index: Poisson arrivals at
     each rate (open loop, native submitter), query lengths log-uniform in
     [31, 10^6] bp, half planted; beside it the plain path (one query per
@@ -183,6 +184,13 @@ def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, pl
         # beyond its capacity the queue only grows, so fewer requests are sent
         n_p = int(min(n, max(200, 2 * plain["queries_per_s"])))
         rec["plain_served"] = replay(n_p, rate, num_streams=1, max_batch_queries=1)
+        if set_launch is not None and rate == rates[0]:
+            # the lowest rate again with every kernel launched on the stream
+            # (single-query batches are otherwise replayed graphs)
+            set_launch(cobs.LAUNCH_DIRECT)
+            rec["direct_launches"] = replay(n, rate, num_streams=streams)
+            rec["plain_served_direct_launches"] = replay(n_p, rate, num_streams=1, max_batch_queries=1)
+            set_launch(cobs.LAUNCH_AUTO)
         out["rates"].append(rec)
         log(f"serving at {rate} q/s: {rec}")
     return out
@@ -469,11 +477,43 @@ def main():
     plain_rate = int(pnt.sum()) / plain_dt
     log(f"plain path: {npq} queries in {plain_dt:.3f}s")
 
+    def set_launch(launch):
+        ix.set_tuning(tuning["unroll"], tuning["chunk"], tuning["order"], launch=launch)
+
+    # the plain path with every kernel launched on the stream (no replayed
+    # graphs), and 1 kbp queries alone (the launch-bound case) both ways
+    set_launch(cobs.LAUNCH_DIRECT)
+    ix.query_flat(subdev, sub.q_off, k=k, topk=0, mode=cobs.MODE_PLAIN)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dnt = ix.query_flat(subdev, sub.q_off, k=k, topk=0, mode=cobs.MODE_PLAIN)[0]
+    torch.cuda.synchronize()
+    plain_direct_rate = int(dnt.sum()) / (time.perf_counter() - t1)
+    one_kbp = {}
+    ones = [qs.get(i)[:1000] for i in range(qs.n) if int(qs.q_off[i + 1] - qs.q_off[i]) >= 1000][:200]
+    for label, launch in (("graph", cobs.LAUNCH_AUTO), ("direct", cobs.LAUNCH_DIRECT)):
+        set_launch(launch)
+        lat = []
+        for rep in range(2):
+            lat = []
+            for x in ones:
+                a = np.frombuffer(x, np.uint8)
+                off = np.array([0, len(x)], np.uint64)
+                t1 = time.perf_counter()
+                ix.query_flat(a, off, k=k, mode=cobs.MODE_PLAIN)
+                lat.append(time.perf_counter() - t1)
+        lat = np.array(lat) * 1e3
+        one_kbp[label] = {"p50_ms": float(np.percentile(lat, 50)),
+                          "p99_ms": float(np.percentile(lat, 99)), "queries": len(ones)}
+    set_launch(cobs.LAUNCH_AUTO)
+    log(f"plain path direct launches: {plain_direct_rate:.4g} lookups/s; 1 kbp alone: {one_kbp}")
+
     serving = None
     if args.serve_rates and args.config == 3:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         serving = serve_measure(cobs, synth, torch, ix, rates, args.serve_pool,
-                                args.serve_seconds, args.serve_max, 100, args.serve_streams)
+                                args.serve_seconds, args.serve_max, 100, args.serve_streams,
+                                set_launch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -524,7 +564,36 @@ def main():
         offload = {"device_budget_gb": args.offload_gb, "groups": oinfo["n_groups"],
                    "stage_bytes": oinfo["stage_bytes"], "ms_per_step": odt * 1e3,
                    "lookups_per_s": lookups / odt, "gather_ms": ogather, "same_hits": same,
-                   "host_link_GBps": info["total_bytes"] / (ogather * 1e-3) / 1e9}
+                   "host_link_GBps": info["total_bytes"] / (ogather * 1e-3) / 1e9,
+                   "mode": "streamed (automatic choice for this batch)"}
+        # small batches read their rows in place from host memory (automatic
+        # below the matrix's bytes); the same queries against the in-HBM hits
+        small = []
+        for nq in (1, 10, 100, 1000):
+            sq = qs.subset(range(min(nq, qs.n)))
+            sdev = torch.from_numpy(sq.bytes.copy()).to("cuda")
+            ix.set_tuning(0, 0, 0, cobs.HOST_READS_AUTO)
+            got = ix.query_flat(sdev, sq.q_off, k=k)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(3):
+                ix.query_flat(sdev, sq.q_off, k=k)
+            torch.cuda.synchronize()
+            sdt = (time.perf_counter() - t1) / 3
+            ix.set_tuning(0, 0, 0, cobs.HOST_READS_STREAM)
+            t1 = time.perf_counter()
+            st_res = ix.query_flat(sdev, sq.q_off, k=k)
+            torch.cuda.synchronize()
+            stream_dt = time.perf_counter() - t1
+            ix.set_tuning(0, 0, 0, cobs.HOST_READS_AUTO)
+            nt_s = int(got[0].sum())
+            small.append({"queries": sq.n, "distinct_terms": nt_s, "ms_per_batch": sdt * 1e3,
+                          "streamed_ms_per_batch": stream_dt * 1e3,
+                          "rows_GBps": nt_s * w.h * row_bytes_per_term / sdt / 1e9,
+                          "same_hits_as_streamed": bool(all(np.array_equal(a, b)
+                                                            for a, b in zip(got, st_res)))})
+            log(f"offloaded, in place: {small[-1]}")
+        offload["in_place"] = small
         log(f"offloaded: {offload}")
 
     traffic = committed_traffic(w.name)
@@ -568,7 +637,9 @@ def main():
         "survivors_per_step": survivors,
         "topk100_ms_per_step": topk_ms,
         "plain_path": {"value": plain_rate, "unit": "lookups/s", "queries": npq,
-                       "speedup_batched": value / plain_rate if plain_rate else None},
+                       "speedup_batched": value / plain_rate if plain_rate else None,
+                       "direct_launches_value": plain_direct_rate,
+                       "one_kbp_latency": one_kbp},
         "build_s": build_s,
         "serving": serving,
         "out_of_core": offload,

@@ -464,7 +464,7 @@ typedef enum {
  *                            batch's terms cross the link, as random reads);
  *  COBS_HOST_READS_AUTO      in place when the batch's rows (bounded by its
  *                            windows: windows x h x row bytes per term) are
- *                            under half the matrix, else streamed.
+ *                            fewer bytes than the matrix, else streamed.
  */
 typedef enum {
     COBS_HOST_READS_AUTO = 0,
@@ -473,14 +473,28 @@ typedef enum {
 } cobs_host_reads;
 
 /*
+ * How a batch of one short query (at most 8,192 windows, not offloaded, no
+ * full scores) is launched.
+ *  COBS_LAUNCH_AUTO    its whole launch sequence (extract, dedup, plan,
+ *                      gather, hit ordering, result copy) is captured once
+ *                      per launch-shape class as a hipGraph and replayed;
+ *  COBS_LAUNCH_DIRECT  every kernel and copy is launched on the stream.
+ */
+typedef enum {
+    COBS_LAUNCH_AUTO = 0,
+    COBS_LAUNCH_DIRECT = 1,
+} cobs_launch;
+
+/*
  * Launch shape of the gather kernel for an index: `unroll` terms whose rows
  * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4), `chunk`, the
  * most distinct terms per work item (longer queries are split and their
  * counts merged; a batch is split into about two work items per resident
- * wavefront, with items of at most `chunk` terms), `order` (cobs_order) and
- * `host_reads` (cobs_host_reads; offloaded indexes only).  0 = defaults (8
- * or 2; 16384; COBS_ORDER_AUTO; COBS_HOST_READS_AUTO).  Results never depend
- * on any of them.
+ * wavefront, with items of at most `chunk` terms), `order` (cobs_order),
+ * `host_reads` (cobs_host_reads; offloaded indexes only) and `launch`
+ * (cobs_launch).  0 = defaults (8 or 2; 16384; COBS_ORDER_AUTO;
+ * COBS_HOST_READS_AUTO; COBS_LAUNCH_AUTO).  Results never depend on any of
+ * them.
  */
 typedef struct {
     uint32_t unroll;
@@ -488,6 +502,7 @@ typedef struct {
     double gather_ms;    /* cobs_tune: the chosen shape's gather time */
     uint32_t order;
     uint32_t host_reads;
+    uint32_t launch;
 } cobs_tuning;
 
 /* Time the gather kernel on the sample batch for every supported unroll and

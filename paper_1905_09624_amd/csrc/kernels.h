@@ -97,7 +97,9 @@ struct GatherArgs {
 // ---- query path ----------------------------------------------------------
 
 // a1: one term per window of every query (kInvalidTerm for DNA windows with
-// a non-ACGT byte).  qstart[i]: first byte of query i; wbase[i]: first window.
+// a non-ACGT byte).  qstart[i]: first byte of query i; wbase[i]: first window;
+// the windows end at wbase[n_queries] (device), total_windows bounds it from
+// above and sets the grid.
 // bytes: 4-byte aligned, with 64 readable bytes after the last query.
 // Also zeroes nterms[0, n_queries).
 hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const uint64_t *wbase,

@@ -119,6 +119,7 @@ __global__ __launch_bounds__(256) void extract_kernel(const uint8_t *bytes, cons
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         nterms[i] = 0;
+    W = min(W, wbase[n]);   // W may bound the windows from above (a replayed launch)
     const uint32_t lane = lane_id();
     const uint64_t tile = 64ull * per_lane;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;

@@ -144,6 +144,9 @@ Workspace::~Workspace()
 {
     for (hipEvent_t &e : ev)
         if (e) (void)hipEventDestroy(e);
+    for (Graph &g : graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (capture) (void)hipStreamDestroy(capture);
 }
 
 cobs_status check_params(const cobs_params *p)

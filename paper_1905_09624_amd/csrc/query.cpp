@@ -160,18 +160,18 @@ cobs_status plan_batch(cobs_index *ix, const BatchSpec &b, BatchPlan &pl)
     pl.gprefix.push_back((uint32_t)pl.groups);
 
     // An offloaded index is read in place (each row slice straight from
-    // pinned host memory over the host link) when the batch's rows are far
-    // fewer than the matrix, else streamed group by group through device
-    // staging buffers.  Random row reads over the link run at about half the
-    // rate of whole-group copies, so in place pays below half the matrix;
-    // the bound uses windows, which bound the distinct terms.
+    // pinned host memory over the host link) when the batch's rows are fewer
+    // than the matrix, else streamed group by group through device staging
+    // buffers.  Random 1 KiB row reads over the link measured as fast as
+    // whole-group copies (55 vs 57 GB/s on the 54 GB index), so the rule
+    // compares bytes; the bound uses windows, which bound the distinct terms.
     if (ix->h_matrix) {
         uint64_t per_term = 0;
         for (const SliceDesc &sd : ix->slices) per_term += sd.width;
         const uint64_t rows_bytes = pl.W * h * per_term;
         const uint32_t mode = b.host_reads ? b.host_reads : ix->tuned_host_reads;
         pl.in_place = mode == COBS_HOST_READS_IN_PLACE ||
-                      (mode == COBS_HOST_READS_AUTO && 2 * rows_bytes < ix->total_bytes);
+                      (mode == COBS_HOST_READS_AUTO && rows_bytes < ix->total_bytes);
     }
     pl.planes = gather_planes_for(pl.maxw);
     int unroll = b.unroll ? (int)b.unroll : (ix->tuned_unroll ? ix->tuned_unroll : gather_default_unroll((int)h));
@@ -301,6 +301,215 @@ static cobs_status gather_streamed(cobs_index *ix, Workspace &ws, GatherArgs ga,
     return COBS_OK;
 }
 
+// ---- single short queries: captured launch sequences ------------------------------
+
+// A batch of one query of at most kGraphMaxWindows windows (dedup in LDS)
+// runs its whole launch sequence -- extract, dedup, plan, gather, hit
+// ordering and the copy of the result head with the first kGraphInlineHits
+// hits -- as one hipGraph, captured once per workspace and launch-shape
+// class and replayed.  The class rounds the windows up to a power of two:
+// the extract grid and the gather grid cover the class's largest query, the
+// kernels read the query's real extent from the uploaded metadata, and the
+// term chunk is the class's, so a replay needs no parameter updates.  Results
+// do not depend on the chunk or the grid.  Only the metadata and query
+// bytes are copied in before the replay.
+constexpr uint64_t kGraphMaxWindows = 8192;
+constexpr uint32_t kGraphInlineHits = 512;
+
+static bool graph_eligible(const cobs_index *ix, const Workspace &ws, const BatchSpec &b,
+                           const BatchPlan &pl, bool timed)
+{
+    return b.n == 1 && !b.full_scores && !b.terms_out && !timed && !ws.graphs_broken &&
+           ix->tuned_launch != COBS_LAUNCH_DIRECT && !ix->h_matrix && pl.maxw <= kGraphMaxWindows &&
+           pl.tslots == 0 && !ix->slices.empty();
+}
+
+// Runs the batch through a replayed graph; *done = false when the batch must
+// take the direct path instead (capture unsupported, candidate overflow).
+static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const BatchSpec &b,
+                                       BatchPlan &pl, hipStream_t st, BatchOut &out, bool *done)
+{
+    *done = false;
+    const uint32_t h = ix->prm.num_hashes, q = ix->prm.q;
+    const uint32_t n_slices = (uint32_t)ix->slices.size();
+    uint64_t wclass = 64;
+    while (wclass < pl.maxw) wclass <<= 1;
+    const uint32_t C = auto_chunk(wclass, n_slices, gather_grid(pl.planes, pl.unroll, (int)h, pl.packed),
+                                  b.chunk_cap ? b.chunk_cap : (ix->tuned_chunk ? ix->tuned_chunk : kDefaultChunkCap));
+    const uint32_t chunk = b.chunk ? b.chunk : C;
+    const uint64_t items = (wclass + chunk - 1) / chunk * n_slices;
+    const int grid = (int)std::min<uint64_t>((uint64_t)gather_grid(pl.planes, pl.unroll, (int)h, pl.packed),
+                                             std::max<uint64_t>(1, (items + 3) / 4));
+    const uint64_t ell_limit = b.score_bits == 16 ? 0xFFFFull : 0xFFFFFFFFull;
+    const uint32_t order = b.order ? b.order : (ix->tuned_order ? ix->tuned_order : default_order(ix));
+
+    // every buffer at the class's size (allocation happens before capture)
+    const size_t meta = pl.meta;
+    const uint64_t max_bytes = wclass + q + 64;
+    COBS_HIP(ws.h_stage.ensure(meta + max_bytes));
+    COBS_HIP(ws.meta.ensure(meta + max_bytes));
+    COBS_HIP(ws.terms.ensure(wclass * 8));
+    COBS_HIP(ws.uterms.ensure(wclass * 8));
+    COBS_HIP(ws.hashes.ensure(wclass * 8 * h));
+    COBS_HIP(ws.table.ensure(8));
+    const size_t head_bytes = sizeof(Scalars) + 8 + 8;
+    COBS_HIP(ws.head.ensure(head_bytes));
+    if (ws.tickets_slots < n_slices || !ws.tickets.p) {
+        COBS_HIP(ws.tickets.ensure(n_slices * 4, true, st));
+        ws.tickets_slots = ws.tickets.cap / 4;
+    }
+    COBS_HIP(ws.qinfo.ensure(sizeof(QInfo)));
+    COBS_HIP(ws.chunk_prefix.ensure(8));
+    COBS_HIP(ws.qorder.ensure(4));
+    COBS_HIP(ws.qcount.ensure(4));
+    uint32_t *accum = b.accum;
+    if (!accum) {
+        if (ws.accum_words < ix->acc_words || !ws.accum.p) {
+            COBS_HIP(ws.accum.ensure(std::max<uint64_t>(ix->acc_words, 64) * 4, true, st));
+            ws.accum_words = ws.accum.cap / 4;
+        }
+        accum = ws.accum.as<uint32_t>();
+    }
+    if (ws.cand_cap == 0) ws.cand_cap = 1 << 20;
+    COBS_HIP(ws.cand_key.ensure(ws.cand_cap * 8));
+    COBS_HIP(ws.cand_q.ensure(ws.cand_cap * 4));
+    COBS_HIP(ws.gstart.ensure(8));
+    COBS_HIP(ws.gcursor.ensure(4));
+    COBS_HIP(ws.seg_a.ensure(ws.cand_cap * 8));
+    COBS_HIP(ws.seg_b.ensure(ws.cand_cap * 8));
+    COBS_HIP(ws.out_id.ensure(std::max<uint64_t>(ws.cand_cap, kGraphInlineHits) * 4));
+    COBS_HIP(ws.out_score.ensure(std::max<uint64_t>(ws.cand_cap, kGraphInlineHits) * 4));
+    const size_t inline_off = (head_bytes + 15) & ~size_t(15);
+    COBS_HIP(ws.h_small.ensure(inline_off + 8 * (size_t)kGraphInlineHits));
+
+    const std::vector<uint64_t> key = {
+        wclass, (uint64_t)pl.planes, (uint64_t)pl.unroll, pl.packed, pl.n_large, chunk, (uint64_t)grid,
+        b.k_num, b.k_den, b.topk, ell_limit, order, b.slots != nullptr, pl.meta, pl.o_lq, ws.cand_cap,
+        (uint64_t)ix->d_matrix, (uint64_t)ws.meta.p, (uint64_t)ws.terms.p, (uint64_t)ws.uterms.p,
+        (uint64_t)ws.hashes.p, (uint64_t)ws.table.p, (uint64_t)ws.head.p, (uint64_t)ws.tickets.p,
+        (uint64_t)ws.qinfo.p, (uint64_t)ws.chunk_prefix.p, (uint64_t)ws.qorder.p, (uint64_t)ws.qcount.p,
+        (uint64_t)accum, (uint64_t)ws.cand_key.p, (uint64_t)ws.cand_q.p, (uint64_t)ws.gstart.p,
+        (uint64_t)ws.gcursor.p, (uint64_t)ws.seg_a.p, (uint64_t)ws.seg_b.p, (uint64_t)ws.out_id.p,
+        (uint64_t)ws.out_score.p, (uint64_t)ws.h_small.p};
+    uint8_t *dmeta = ws.meta.as<uint8_t>();
+    const MetaPtrs mp = meta_ptrs(pl, dmeta, b.slots != nullptr);
+    Scalars *dsc = ws.head.as<Scalars>();
+    uint32_t *d_nterms = (uint32_t *)(ws.head.as<uint8_t>() + sizeof(Scalars));
+    uint32_t *d_out_n = d_nterms + 1;
+    uint32_t *d_out_start = d_out_n + 1;
+    uint8_t *hs = ws.h_small.as<uint8_t>();
+
+    hipGraphExec_t exec = nullptr;
+    for (const Workspace::Graph &g : ws.graphs)
+        if (g.key == key) exec = g.exec;
+    if (!exec) {
+        if (!ws.capture) COBS_HIP(hipStreamCreateWithFlags(&ws.capture, hipStreamNonBlocking));
+        hipStream_t cs = ws.capture;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            (void)hipGetLastError();
+            ws.graphs_broken = true;
+            return COBS_OK;
+        }
+        BatchPlan cp = pl;
+        cp.W = wclass;   // grid bound; the kernels stop at the query's real windows
+        GatherArgs ga{};
+        ga.matrix = ix->d_matrix;
+        ga.slices = ix->d_slices;
+        ga.order = ix->d_order;
+        ga.hashes = ws.hashes.as<uint64_t>();
+        ga.qinfo = ws.qinfo.as<QInfo>();
+        ga.qorder = ws.qorder.as<uint32_t>();
+        ga.chunk_prefix = ws.chunk_prefix.as<uint32_t>();
+        ga.work_counter = &dsc->work_counter;
+        ga.tickets = ws.tickets.as<uint32_t>();
+        ga.accum = accum;
+        ga.acc_words = ix->acc_words;
+        ga.cand_counter = &dsc->cand_counter;
+        ga.cand_key = ws.cand_key.as<uint64_t>();
+        ga.cand_q = ws.cand_q.as<uint32_t>();
+        ga.qcount = ws.qcount.as<uint32_t>();
+        ga.cand_cap = ws.cand_cap;
+        ga.n_queries = 1;
+        ga.n_slices = n_slices;
+        ga.h = h;
+        ga.chunk = chunk;
+        ga.topk = b.topk;
+        ga.n_docs = ix->n_docs;
+        ga.slice_major = order == COBS_ORDER_SLICES ? 1u : 0u;
+        hipError_t e = launch_front(ix, cp, mp, dmeta + meta, ws.terms.as<uint64_t>(), ws.table.as<uint64_t>(),
+                                    ws.uterms.as<uint64_t>(), ws.hashes.as<uint64_t>(), d_nterms, cs);
+        if (e == hipSuccess)
+            e = launch_plan(d_nterms, mp.wbase, mp.slot, 1, chunk, n_slices, b.k_num, b.k_den, ell_limit,
+                            ws.qinfo.as<QInfo>(), ws.qorder.as<uint32_t>(), ws.chunk_prefix.as<uint32_t>(),
+                            &dsc->total_items, &dsc->work_counter, &dsc->cand_counter, ws.qcount.as<uint32_t>(),
+                            &dsc->flags, cs);
+        if (e == hipSuccess) e = launch_gather(ga, pl.planes, pl.unroll, grid, pl.packed, cs);
+        if (e == hipSuccess)
+            e = launch_group_sort(ws.cand_key.as<uint64_t>(), ws.cand_q.as<uint32_t>(), &dsc->cand_counter,
+                                  ws.cand_cap, 1, b.topk, ws.qcount.as<uint32_t>(), ws.gstart.as<uint32_t>(),
+                                  ws.gcursor.as<uint32_t>(), ws.seg_a.as<uint64_t>(), ws.seg_b.as<uint64_t>(),
+                                  d_out_start, d_out_n, ws.out_id.as<uint32_t>(), ws.out_score.as<uint32_t>(), cs);
+        if (e == hipSuccess) e = hipMemcpyAsync(hs, ws.head.p, head_bytes, hipMemcpyDeviceToHost, cs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hs + inline_off, ws.out_id.p, 4 * (size_t)kGraphInlineHits, hipMemcpyDeviceToHost, cs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hs + inline_off + 4 * (size_t)kGraphInlineHits, ws.out_score.p,
+                               4 * (size_t)kGraphInlineHits, hipMemcpyDeviceToHost, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = ee;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ws.graphs_broken = true;
+            return COBS_OK;
+        }
+        ws.graphs.push_back(Workspace::Graph{key, exec});
+    }
+
+    // this query: metadata and bytes in, replay, head and first hits back
+    uint8_t *stg = ws.h_stage.as<uint8_t>();
+    write_meta(pl, b.slots, stg);
+    if (b.mem == COBS_MEM_HOST) {
+        if (pl.nbytes) std::memcpy(stg + meta, b.bytes + pl.byte0, pl.nbytes);
+        COBS_HIP(hipMemcpyAsync(dmeta, stg, meta + pl.nbytes, hipMemcpyHostToDevice, st));
+    } else {
+        COBS_HIP(hipMemcpyAsync(dmeta, stg, meta, hipMemcpyHostToDevice, st));
+        if (pl.nbytes)
+            COBS_HIP(hipMemcpyAsync(dmeta + meta, b.bytes + pl.byte0, pl.nbytes, hipMemcpyDeviceToDevice, st));
+    }
+    COBS_HIP(hipGraphLaunch(exec, st));
+    COBS_HIP(hipStreamSynchronize(st));
+    Scalars sc;
+    std::memcpy(&sc, hs, sizeof(Scalars));
+    if (sc.flags & 1u) return set_error(COBS_EOVERFLOW, "a query exceeds the score width");
+    if (sc.cand_counter > ws.cand_cap) return COBS_OK;   // the direct path enlarges the buffers
+    uint32_t nt, nh, st2[2];
+    std::memcpy(&nt, hs + sizeof(Scalars), 4);
+    std::memcpy(&nh, hs + sizeof(Scalars) + 4, 4);
+    std::memcpy(st2, hs + sizeof(Scalars) + 8, 8);
+    out.num_terms[0] = nt;
+    out.n[0] = nh;
+    out.start[0] = st2[0];
+    out.start[1] = st2[1];
+    const uint64_t total = st2[1];
+    if (total <= kGraphInlineHits) {
+        out.ids = (const uint32_t *)(hs + inline_off);
+        out.scores = (const uint32_t *)(hs + inline_off + 4 * (size_t)kGraphInlineHits);
+    } else {
+        COBS_HIP(ws.h_out.ensure(total * 8));
+        uint32_t *ho = ws.h_out.as<uint32_t>();
+        COBS_HIP(hipMemcpyAsync(ho, ws.out_id.p, total * 4, hipMemcpyDeviceToHost, st));
+        COBS_HIP(hipMemcpyAsync(ho + total, ws.out_score.p, total * 4, hipMemcpyDeviceToHost, st));
+        COBS_HIP(hipStreamSynchronize(st));
+        out.ids = ho;
+        out.scores = ho + total;
+    }
+    *done = true;
+    return COBS_OK;
+}
+
 cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStream_t st,
                       BatchOut &out)
 {
@@ -318,6 +527,11 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         if (ps != COBS_OK) return ps;
     }
     if (ix->h_matrix && !pl.in_place) streaming.lock();   // one streamed batch at a time
+    if (graph_eligible(ix, ws, b, pl, g_prof.load() != 0 || b.time_gather)) {
+        bool done = false;
+        cobs_status gs = run_single_replayed(ix, ws, b, pl, st, out, &done);
+        if (gs != COBS_OK || done) return gs;
+    }
     const uint64_t W = pl.W, tslots = pl.tslots, nbytes = pl.nbytes, byte0 = pl.byte0;
     const int planes = pl.planes, unroll = pl.unroll, grid = pl.grid;
     const bool packed = pl.packed;
@@ -820,10 +1034,12 @@ cobs_status cobs_set_tuning(cobs_index *ix, const cobs_tuning *t)
         return set_error(COBS_EINVAL, "unsupported unroll for this index");
     if (t->order > COBS_ORDER_SLICES) return set_error(COBS_EINVAL, "unknown work-item order");
     if (t->host_reads > COBS_HOST_READS_IN_PLACE) return set_error(COBS_EINVAL, "unknown host_reads");
+    if (t->launch > COBS_LAUNCH_DIRECT) return set_error(COBS_EINVAL, "unknown launch");
     ix->tuned_unroll = (int)t->unroll;
     ix->tuned_chunk = t->chunk;
     ix->tuned_order = t->order;
     ix->tuned_host_reads = t->host_reads;
+    ix->tuned_launch = t->launch;
     return COBS_OK;
 }
 
@@ -836,7 +1052,7 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
     const uint32_t chunks[] = {0, 512, 1024, 2048, 4096, 8192, 16384, 1u << 20};
     Workspace *ws = acquire_workspace(ix);
     const uint32_t order0 = default_order(ix);
-    cobs_tuning win{0, 0, 1e300, order0, ix->tuned_host_reads};
+    cobs_tuning win{0, 0, 1e300, order0, ix->tuned_host_reads, ix->tuned_launch};
     cobs_status s = COBS_OK;
     auto time_shape = [&](int u, uint32_t c, uint32_t order) -> double {
         BatchSpec spec;
@@ -864,7 +1080,8 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
         for (uint32_t c : chunks) {
             const double t = time_shape(u, c, order0);
             if (s != COBS_OK) break;
-            if (t < win.gather_ms) win = cobs_tuning{(uint32_t)u, c, t, order0, ix->tuned_host_reads};
+            if (t < win.gather_ms)
+                win = cobs_tuning{(uint32_t)u, c, t, order0, ix->tuned_host_reads, ix->tuned_launch};
         }
         if (s != COBS_OK) break;
     }
@@ -872,7 +1089,7 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
         const uint32_t other = order0 == COBS_ORDER_SLICES ? COBS_ORDER_QUERIES : COBS_ORDER_SLICES;
         const double t = time_shape((int)win.unroll, win.chunk, other);
         if (s == COBS_OK && t < win.gather_ms)
-            win = cobs_tuning{win.unroll, win.chunk, t, other, ix->tuned_host_reads};
+            win = cobs_tuning{win.unroll, win.chunk, t, other, ix->tuned_host_reads, ix->tuned_launch};
     }
     release_workspace(ix, ws);
     if (s != COBS_OK) return s;

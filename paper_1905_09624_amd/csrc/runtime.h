@@ -74,6 +74,16 @@ struct Workspace {
     uint64_t accum_words = 0;
     uint64_t cand_cap = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};   // gather timing (cobs_profile)
+    // Captured launch sequences of single short queries (run_batch), one per
+    // launch-shape class, replayed with hipGraphLaunch; each remembers the
+    // buffer addresses it was captured with.
+    struct Graph {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t capture = nullptr;   // private stream the sequences are captured on
+    bool graphs_broken = false;      // capture failed once: direct launches only
     ~Workspace();
 };
 
@@ -140,6 +150,7 @@ struct cobs_index {
     uint8_t *h_matrix = nullptr;
     uint8_t *h_dev_matrix = nullptr;   // device address of h_matrix (rows read in place)
     uint32_t tuned_host_reads = 0;     // cobs_tuning.host_reads
+    uint32_t tuned_launch = 0;         // cobs_tuning.launch
     std::vector<Group> groups;
     cobs::SliceDesc *d_group_slices = nullptr;   // slices, base relative to their group
     uint8_t *d_stage[2] = {nullptr, nullptr};

@@ -284,6 +284,19 @@ def test_compact_100k_full_size_whole_blocks_and_served():
     base = len(bench_q) + len(planted)
     _compare_hits(want[base:], batch, qset.ell[base:], _checked(groups), w5.k)
 
+    # out of core at full size: the matrix in pinned host memory, the bench
+    # and planted queries read in place (their rows are far fewer than the
+    # matrix), scores and hits against the oracle on the checked documents
+    data, off = _pack(bench_q + planted)
+    n_q = len(bench_q) + len(planted)
+    ix.offload(30 * 10**9)
+    assert ix.info()["host_resident"]
+    ix.set_tuning(host_reads=cobs.HOST_READS_IN_PLACE)
+    osc, ont = ix.scores(data, off)
+    _compare_scores(want[:n_q], osc, ont, qset.ell[:n_q], _checked(groups), "in place")
+    _compare_hits(want[:n_q], ix.query(data, off, k=w.k), qset.ell[:n_q], _checked(groups), w.k)
+    ix.set_tuning()
+
 
 def test_classic_10k_full_size_columns():
     # 10,000 documents in one block of 2.8 M rows x 1,280 bytes: the first

@@ -53,3 +53,25 @@ def test_read_bandwidth():
                                           ctypes.byref(r)) == cobs.EINVAL
     assert cobs.lib().cobs_read_bandwidth(ctypes.c_void_p(buf.data_ptr()), 1000, None,
                                           ctypes.byref(r)) == cobs.EINVAL
+
+
+def test_read_rows_bandwidth():
+    # random 1 KiB row reads: a working set that fits the L2 reads faster than
+    # one that only HBM holds; malformed buffers are refused
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_09624_amd as cobs
+    buf = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    small = cobs.read_rows_bandwidth(buf[:2 << 20], 8 << 20, cached=True)
+    big = cobs.read_rows_bandwidth(buf, 8 << 20, cached=False)
+    assert 500 < big < 20000 and small > big
+    import ctypes
+    r = ctypes.c_double()
+    L = cobs.lib()
+    assert L.cobs_read_rows_bandwidth(ctypes.c_void_p(buf.data_ptr() + 8), 1 << 20, 1000, 1, None,
+                                      ctypes.byref(r)) == cobs.EINVAL
+    assert L.cobs_read_rows_bandwidth(ctypes.c_void_p(buf.data_ptr()), 512, 1000, 1, None,
+                                      ctypes.byref(r)) == cobs.EINVAL
+    assert L.cobs_read_rows_bandwidth(ctypes.c_void_p(buf.data_ptr()), 1 << 20, 0, 1, None,
+                                      ctypes.byref(r)) == cobs.EINVAL

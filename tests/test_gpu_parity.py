@@ -242,6 +242,43 @@ def test_planted_source_never_missed(workload):
         assert np.all(sc[i] >= ex)
 
 
+def test_single_queries_replayed_graphs_equal_direct_and_oracle(workload):
+    # single short queries run as replayed hipGraphs (one per launch-shape
+    # class); every replay is checked against the oracle and the direct
+    # launches, with batched work and synchronisations between the replays,
+    # each class replayed many times, and one query too long for a graph
+    import torch
+    cobs = _cobs()
+    w, d, qs, gix, oix = workload
+    rng = np.random.default_rng(11)
+    base = [qs.get(i) for i in range(qs.n)]
+    strings = [b""]
+    for L in (31, 40, 100, 200, 500, 1000, 2500, 4000, 6000, 8200, 9000):
+        s = base[int(rng.integers(0, len(base)))]
+        strings.append((s * (L // max(len(s), 1) + 1))[:L])
+    strings += base[:8]
+    want = {}
+    for k, topk in (((4, 5), 0), ((0, 1), 5)):
+        for rep in range(3):
+            for x in strings:
+                data = np.frombuffer(x, np.uint8) if x else np.zeros(0, np.uint8)
+                off = np.array([0, len(x)], np.uint64)
+                got = {}
+                for launch in (cobs.LAUNCH_AUTO, cobs.LAUNCH_DIRECT):
+                    gix.set_tuning(launch=launch)
+                    got[launch] = gix.query(data, off, k=k, topk=topk)[0]
+                gix.set_tuning()
+                kk = (x, k, topk)
+                if kk not in want:
+                    want[kk] = oix.query(x, k[0], k[1], topk)
+                ids, sc, l = want[kk]
+                for g in got.values():
+                    assert g[2] == l and np.array_equal(g[0], ids) and np.array_equal(g[1], sc), (len(x), k)
+            # eager batched work between the rounds of replays
+            gix.query(qs.bytes, qs.q_off, k=(1, 2))
+            torch.cuda.synchronize()
+
+
 # ---- edge cases -----------------------------------------------------------------
 
 def test_edge_queries():
