@@ -316,6 +316,35 @@ cobs_status cobs_query_scores(cobs_index *ix, const uint8_t *bytes,
                               uint32_t *num_terms);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * full score vectors as cobs_query_scores, computed without any device
+ * allocation.  Every intermediate buffer of the batch (query bytes, terms,
+ * hash sets, hashes, plan, tickets, score buffers of split queries) is
+ * carved out of one fixed scratch array of 64 MiB that the library holds on
+ * each device it runs on until the process ends; a batch that needs more
+ * fails with EBUDGET (8 (2 + h) bytes per window, up to 32 more per window
+ * of queries longer than 8,192 windows, and 4 bytes per document for every
+ * query longer than one work item).
+ *  bytes     device memory: query i is bytes[q_off[i] .. q_off[i+1])
+ *  q_off     host array [n_queries + 1], non-decreasing
+ *  scores    device memory, caller-owned [n_queries * n_docs] u32:
+ *            scores[i * n_docs + d] = score of query i for input document d
+ *  num_terms device memory [n_queries] u32 (l of each query), or NULL
+ * The current device must be the index's; the index must be resident in
+ * HBM (not offloaded).  Asynchronous: the work is queued on `stream` and the
+ * outputs are valid once it completes.  Every call on one device shares its
+ * scratch array, so calls whose work overlaps on the device race (use one
+ * stream, or order the streams); the scratch array keeps the last call's
+ * contents and each call clears what must start at zero.
+ * Errors: EINVAL, EBUDGET, EDEVICE.
+ */
+cobs_status cobs_query_scores_noalloc(cobs_index *ix, const uint8_t *bytes,
+                                      const uint64_t *q_off, uint32_t n_queries,
+                                      void *stream, uint32_t *scores,
+                                      uint32_t *num_terms);
+
+/*
  * Distinct terms of each query (steps before the gather): terms of query i
  * go to terms[cap_off[i] ..], cap_off[i] = sum over j < i of
  * max(0, len_j - q + 1); num_terms[i] receives l.  The order within a query

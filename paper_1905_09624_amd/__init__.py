@@ -122,6 +122,8 @@ EXPORTS = {
                                    C.POINTER(QueryOpts), C.c_void_p, C.POINTER(C.POINTER(Hits))]),
     "cobs_query_scores": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cobs_query_scores_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                                            C.c_void_p, C.c_void_p, C.c_void_p]),
     "cobs_query_terms": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
                                    C.c_void_p, C.c_void_p, C.c_void_p]),
     "cobs_hits_free": (None, [C.POINTER(Hits), C.c_uint32]),
@@ -429,6 +431,26 @@ class Index:
         nt = np.zeros(max(n, 1), np.uint32)
         _check(lib().cobs_query_scores(self._h, ptr, _p(qo), n, mem, _stream(stream), _p(sc), _p(nt)))
         return sc[:n, :nd], nt[:n]
+
+    def scores_noalloc(self, data, q_off, scores, num_terms=None, stream=None):
+        """Full scores into caller-owned device tensors without any device
+        allocation (cobs_query_scores_noalloc): data is a device uint8 tensor,
+        scores a device int32/uint32 tensor of n_queries * n_docs elements,
+        num_terms one of n_queries elements or None.  Asynchronous on the
+        stream (torch's current one by default)."""
+        qo = np.ascontiguousarray(q_off, dtype=np.uint64)
+        n = len(qo) - 1
+        nd = self.info()["n_docs"]
+        if not data.is_cuda or not scores.is_cuda or (num_terms is not None and not num_terms.is_cuda):
+            raise ValueError("data, scores and num_terms must be device tensors")
+        if scores.numel() * scores.element_size() < n * nd * 4:
+            raise ValueError("scores holds fewer than n_queries * n_docs 32-bit words")
+        if num_terms is not None and num_terms.numel() * num_terms.element_size() < n * 4:
+            raise ValueError("num_terms holds fewer than n_queries 32-bit words")
+        _check(lib().cobs_query_scores_noalloc(
+            self._h, C.c_void_p(data.data_ptr()), _p(qo), n, _stream(stream),
+            C.c_void_p(scores.data_ptr()),
+            C.c_void_p(num_terms.data_ptr()) if num_terms is not None else None))
 
     def terms(self, data, q_off, q: int, stream=None):
         """Distinct terms of each query (unordered within a query)."""

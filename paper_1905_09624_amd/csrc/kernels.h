@@ -172,6 +172,16 @@ hipError_t launch_insert(const uint8_t *bytes, const StrDesc *strs, uint32_t n_s
                          TermSpec ts, Seeds seeds, hipStream_t st);
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+
+// Scratch memory of the allocation-free query entry point: one file-scope
+// device array of kScratchBytes, loaded with the library on every device it
+// runs on and held until the process ends.  scratch_address gives its address
+// on the current device (looked up once per device with
+// hipGetSymbolAddress); host code passes that address to kernels, never the
+// array's host-side name.
+constexpr uint64_t kScratchBytes = 64ull << 20;
+hipError_t scratch_address(void **ptr);
 
 // One read pass over bytes / 16 16-byte words at p (16-byte aligned) by
 // kReadGrid workgroups of 256 threads; pattern 0: per-wavefront chunks of

@@ -16,6 +16,8 @@
 #include "device_util.h"
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 namespace cobs {
 namespace {
@@ -605,6 +607,12 @@ __global__ void concat_rows_kernel(const uint32_t *a, uint64_t a_words, uint32_t
     }
 }
 
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
 __global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -833,6 +841,13 @@ hipError_t launch_read_rows(const void *p, uint64_t bytes, uint64_t per_wave, bo
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_read(const void *p, uint64_t bytes, int pattern, uint32_t *sink, hipStream_t st)
 {
     const uint64_t n = bytes / 16;
@@ -842,6 +857,31 @@ hipError_t launch_read(const void *p, uint64_t bytes, int pattern, uint32_t *sin
     else
         hipLaunchKernelGGL(read_sweep_kernel, dim3(kReadGrid), dim3(256), 0, st, (const u32x4 *)p, n, sink);
     return hipGetLastError();
+}
+
+// The allocation-free entry point's scratch memory.  In host code `scratch`
+// names a host-side stand-in, not device memory: only the address that
+// hipGetSymbolAddress returns for the current device may reach a kernel.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+hipError_t scratch_address(void **ptr)
+{
+    static std::mutex mu;
+    static std::vector<void *> addr;   // per device
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(mu);
+    if (addr.size() <= (size_t)dev) addr.resize((size_t)dev + 1, nullptr);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace cobs

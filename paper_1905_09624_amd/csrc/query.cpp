@@ -1007,6 +1007,101 @@ cobs_status cobs_query_scores(cobs_index *ix, const uint8_t *bytes, const uint64
     return s;
 }
 
+cobs_status cobs_query_scores_noalloc(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_off,
+                                     uint32_t n_queries, void *stream, uint32_t *scores,
+                                     uint32_t *num_terms)
+{
+    if (!ix || (!scores && n_queries && ix->n_docs)) return set_error(COBS_EINVAL, "NULL argument");
+    if (n_queries == 0) return COBS_OK;
+    if (ix->h_matrix) return set_error(COBS_EINVAL, "the index is offloaded to host memory");
+    int dev = -1;
+    COBS_HIP(hipGetDevice(&dev));
+    if (dev != ix->device) return set_error(COBS_EINVAL, "the index lives on another device than the current one");
+    hipStream_t st = (hipStream_t)stream;
+    BatchSpec spec;
+    spec.bytes = bytes;
+    spec.q_off = q_off;
+    spec.n = n_queries;
+    spec.mem = COBS_MEM_DEVICE;
+    BatchPlan pl;
+    {
+        cobs_status ps = plan_batch(ix, spec, pl);
+        if (ps != COBS_OK) return ps;
+    }
+    const uint32_t n = n_queries, h = ix->prm.num_hashes;
+    const uint32_t n_slices = (uint32_t)ix->slices.size();
+    // carve every buffer of the batch out of the scratch array
+    uint64_t used = 0;
+    auto take = [&](uint64_t bytes_) {
+        const uint64_t at = used;
+        used += (bytes_ + 255) & ~255ull;
+        return at;
+    };
+    const uint64_t w1 = std::max<uint64_t>(pl.W, 1);
+    const uint64_t o_meta = take(pl.meta), o_bytes = take(pl.nbytes + 64);
+    const uint64_t o_terms = take(w1 * 8), o_uterms = take(w1 * 8), o_hashes = take(w1 * 8 * h);
+    const uint64_t o_table = take(std::max<uint64_t>(pl.tslots, 1) * 8);
+    const uint64_t o_head = take(sizeof(Scalars) + (uint64_t)n * 4);
+    const uint64_t o_qinfo = take((uint64_t)n * sizeof(QInfo)), o_qorder = take((uint64_t)n * 4);
+    const uint64_t o_cpre = take((uint64_t)(n + 1) * 4), o_qcount = take((uint64_t)n * 4);
+    // tickets and score buffers start at zero: one contiguous cleared range
+    const uint64_t o_zero = used;
+    const uint64_t o_tickets = take((uint64_t)n * n_slices * 4);
+    const uint64_t o_accum = take(std::max<uint64_t>(pl.pslots * ix->acc_words, 64) * 4);
+    const uint64_t zero_bytes = used - o_zero;
+    if (used > kScratchBytes)
+        return set_error(COBS_EBUDGET, "the batch needs " + std::to_string(used) +
+                                           " bytes of scratch memory; this entry point has " +
+                                           std::to_string(kScratchBytes));
+    void *base_p = nullptr;
+    COBS_HIP(scratch_address(&base_p));
+    uint8_t *base = (uint8_t *)base_p;
+
+    std::vector<uint8_t> meta(pl.meta);
+    write_meta(pl, nullptr, meta.data());
+    COBS_HIP(hipMemcpyAsync(base + o_meta, meta.data(), pl.meta, hipMemcpyHostToDevice, st));
+    if (pl.nbytes)
+        COBS_HIP(hipMemcpyAsync(base + o_bytes, bytes + pl.byte0, pl.nbytes, hipMemcpyDeviceToDevice, st));
+    const MetaPtrs mp = meta_ptrs(pl, base + o_meta, false);
+    Scalars *dsc = (Scalars *)(base + o_head);
+    uint32_t *d_nterms = (uint32_t *)(base + o_head + sizeof(Scalars));
+    COBS_HIP(launch_front(ix, pl, mp, base + o_bytes, (uint64_t *)(base + o_terms), (uint64_t *)(base + o_table),
+                          (uint64_t *)(base + o_uterms), (uint64_t *)(base + o_hashes), d_nterms, st));
+    COBS_HIP(launch_fill_u64((uint64_t *)(base + o_zero), zero_bytes / 8, 0, st));
+    COBS_HIP(launch_plan(d_nterms, mp.wbase, nullptr, n, pl.chunk, n_slices, 0, 1, 0xFFFFFFFFull,
+                         (QInfo *)(base + o_qinfo), (uint32_t *)(base + o_qorder),
+                         (uint32_t *)(base + o_cpre), &dsc->total_items, &dsc->work_counter,
+                         &dsc->cand_counter, (uint32_t *)(base + o_qcount), &dsc->flags, st));
+    // a query without terms has no work items: its scores stay zero
+    COBS_HIP(launch_fill_u32(scores, (uint64_t)n * ix->n_docs, 0, st));
+    GatherArgs ga{};
+    ga.matrix = ix->d_matrix;
+    ga.slices = ix->d_slices;
+    ga.order = ix->d_order;
+    ga.hashes = (const uint64_t *)(base + o_hashes);
+    ga.qinfo = (const QInfo *)(base + o_qinfo);
+    ga.qorder = (const uint32_t *)(base + o_qorder);
+    ga.chunk_prefix = (const uint32_t *)(base + o_cpre);
+    ga.work_counter = &dsc->work_counter;
+    ga.tickets = (uint32_t *)(base + o_tickets);
+    ga.accum = (uint32_t *)(base + o_accum);
+    ga.acc_words = ix->acc_words;
+    ga.cand_counter = &dsc->cand_counter;
+    ga.qcount = (uint32_t *)(base + o_qcount);
+    ga.full_scores = scores;
+    ga.n_queries = n;
+    ga.n_slices = n_slices;
+    ga.h = h;
+    ga.chunk = pl.chunk;
+    ga.n_docs = ix->n_docs;
+    const uint32_t order = ix->tuned_order ? ix->tuned_order : default_order(ix);
+    ga.slice_major = order == COBS_ORDER_SLICES ? 1u : 0u;
+    if (n_slices) COBS_HIP(launch_gather(ga, pl.planes, pl.unroll, pl.grid, pl.packed, st));
+    if (num_terms)
+        COBS_HIP(hipMemcpyAsync(num_terms, d_nterms, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+    return COBS_OK;
+}
+
 cobs_status cobs_query_terms(const cobs_index *cix, const uint8_t *bytes, const uint64_t *q_off,
                              uint32_t n_queries, uint32_t mem, void *stream, uint64_t *terms,
                              uint32_t *num_terms)
