@@ -399,6 +399,19 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
     uint32_t *d_out_start = d_out_n + 1;
     uint8_t *hs = ws.h_small.as<uint8_t>();
 
+    // the first 16 entries describe the launch shapes, the rest the buffer
+    // addresses: a graph captured with other addresses can never be replayed
+    // again (a buffer has grown since), so it is dropped
+    constexpr size_t kShapeKeys = 16;
+    for (size_t i = 0; i < ws.graphs.size();) {
+        const std::vector<uint64_t> &k = ws.graphs[i].key;
+        if (!std::equal(k.begin() + kShapeKeys, k.end(), key.begin() + kShapeKeys)) {
+            (void)hipGraphExecDestroy(ws.graphs[i].exec);
+            ws.graphs.erase(ws.graphs.begin() + (long)i);
+        } else {
+            ++i;
+        }
+    }
     hipGraphExec_t exec = nullptr;
     for (const Workspace::Graph &g : ws.graphs)
         if (g.key == key) exec = g.exec;
