@@ -502,12 +502,14 @@ typedef enum {
 } cobs_host_reads;
 
 /*
- * How a batch of one short query (at most 8,192 windows, not offloaded, no
+ * How a batch of one short query (at most 2,048 windows, not offloaded, no
  * full scores) is launched.
- *  COBS_LAUNCH_AUTO    its whole launch sequence (extract, dedup, plan,
- *                      gather, hit ordering, result copy) is captured once
- *                      per launch-shape class as a hipGraph and replayed;
- *  COBS_LAUNCH_DIRECT  every kernel and copy is launched on the stream.
+ *  COBS_LAUNCH_AUTO    three kernels (terms, set and plan in one workgroup;
+ *                      the gather; the hits sorted in one workgroup) and the
+ *                      result copy, captured once per launch-shape class as a
+ *                      hipGraph and replayed;
+ *  COBS_LAUNCH_DIRECT  the general pipeline, every kernel and copy launched on
+ *                      the stream.
  */
 typedef enum {
     COBS_LAUNCH_AUTO = 0,

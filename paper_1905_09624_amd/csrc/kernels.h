@@ -160,6 +160,25 @@ hipError_t launch_group_sort(const uint64_t *cand_key, const uint32_t *cand_q,
                              uint32_t *out_n, uint32_t *out_id, uint32_t *out_score,
                              hipStream_t st);
 
+// A batch of one query of at most max_windows <= kLdsTableSlots / 2
+// windows: a1-a3 and the plan in one workgroup (terms straight into an LDS
+// set); the same outputs as launch_extract + launch_dedup + launch_plan with
+// n_queries = 1.  bytes: the query, 4-byte aligned, 64 readable bytes after.
+hipError_t launch_front_one(const uint8_t *bytes, const uint64_t *wbase, uint64_t max_windows,
+                            const uint32_t *slot, uint64_t *uterms, uint64_t *hashes,
+                            uint32_t *nterms, TermSpec ts, Seeds seeds, uint32_t chunk,
+                            uint32_t n_slices, uint32_t k_num, uint32_t k_den, uint64_t ell_limit,
+                            QInfo *qinfo, uint32_t *qorder, uint32_t *chunk_prefix,
+                            uint64_t *total_items, unsigned long long *work_counter,
+                            unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags,
+                            hipStream_t st);
+// The hits of a batch of one query, sorted in place in cand_key (tmp: as
+// many keys of scratch): out_start[0..1], out_n[0], out_id, out_score as
+// launch_group_sort writes them for n_queries = 1.
+hipError_t launch_sort_one(uint64_t *cand_key, uint64_t *tmp, const unsigned long long *n_cand,
+                           uint64_t cap, uint32_t topk, uint32_t *out_start, uint32_t *out_n,
+                           uint32_t *out_id, uint32_t *out_score, hipStream_t st);
+
 // ---- construction ------------------------------------------------------------
 
 hipError_t launch_count(const uint8_t *bytes, const StrDesc *strs, uint32_t n_strs,

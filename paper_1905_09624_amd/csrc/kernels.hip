@@ -166,13 +166,14 @@ __device__ __forceinline__ bool set_insert(uint64_t *table, uint64_t cap, uint64
     }
 }
 
-// Windows [b, e) of one query: insert every valid term; each wavefront
+// Windows [b, e) of one query: insert every valid term (term_at(w): the
+// term of window w, kInvalidTerm for an invalid DNA window); each wavefront
 // reserves output positions for its new terms with one atomic add on count.
-template <int kScope>
-__device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint64_t *flag,
-                                            const uint64_t *terms, uint64_t w0, uint64_t b,
-                                            uint64_t e, uint64_t *uterms, uint64_t *hashes,
-                                            TermSpec ts, const Seeds &seeds, uint32_t *count)
+template <int kScope, typename TermAt>
+__device__ __forceinline__ void dedup_windows(uint64_t *table, uint64_t cap, uint64_t *flag,
+                                              TermAt term_at, uint64_t w0, uint64_t b,
+                                              uint64_t e, uint64_t *uterms, uint64_t *hashes,
+                                              TermSpec ts, const Seeds &seeds, uint32_t *count)
 {
     const uint32_t lane = lane_id();
     for (uint64_t base = b; base < e; base += blockDim.x) {
@@ -180,7 +181,7 @@ __device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint6
         bool fresh = false;
         uint64_t t = 0, hs[kMaxHashes];
         if (w < e) {
-            t = terms[w0 + w];
+            t = term_at(w);
             if (ts.kind == 1 || t != kInvalidTerm) {
 #pragma unroll
                 for (int i = 0; i < kMaxHashes; ++i)
@@ -203,6 +204,17 @@ __device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint6
                 if (i < (int)ts.h) hashes[pos * ts.h + i] = hs[i];
         }
     }
+}
+
+// The same over the terms the extract kernel wrote (terms[w0 + w]).
+template <int kScope>
+__device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint64_t *flag,
+                                            const uint64_t *terms, uint64_t w0, uint64_t b,
+                                            uint64_t e, uint64_t *uterms, uint64_t *hashes,
+                                            TermSpec ts, const Seeds &seeds, uint32_t *count)
+{
+    dedup_windows<kScope>(table, cap, flag, [&](uint64_t w) { return terms[w0 + w]; }, w0, b, e,
+                          uterms, hashes, ts, seeds, count);
 }
 
 // One workgroup per query whose set fits in kSlots LDS slots (lds_q: those
@@ -363,6 +375,61 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint32_t *nterms, cons
     }
 }
 
+// ---- one short query: terms, set and plan in one workgroup ---------------------------------
+
+// A batch of one query of at most kSlots / 2 windows: every window's term is
+// computed and inserted into an LDS set directly (no term array), then the
+// query's plan is written as plan_kernel writes it for n = 1.  bytes: the
+// query (4-byte aligned, 64 readable bytes after it); wbase[0..1]: its
+// windows.
+template <uint32_t kSlots, int kThreads>
+__global__ __launch_bounds__(kThreads) void front_one_kernel(
+    const uint8_t *bytes, const uint64_t *wbase, const uint32_t *slot, uint64_t *uterms,
+    uint64_t *hashes, uint32_t *nterms, TermSpec ts, Seeds seeds, uint32_t chunk, uint32_t n_slices,
+    uint32_t k_num, uint32_t k_den, uint64_t ell_limit, QInfo *qinfo, uint32_t *qorder,
+    uint32_t *chunk_prefix, uint64_t *total_items, unsigned long long *work_counter,
+    unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags)
+{
+    __shared__ uint64_t ltable[kSlots];
+    __shared__ uint64_t lflag;
+    __shared__ uint32_t lcount;
+    const uint64_t nw = wbase[1] - wbase[0];
+    const uint64_t cap = table_cap(nw);
+    if (threadIdx.x == 0) { lcount = 0; lflag = kEmpty; }
+    for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) ltable[s] = kEmpty;
+    __syncthreads();
+    dedup_windows<__HIP_MEMORY_SCOPE_WORKGROUP>(
+        ltable, cap, &lflag,
+        [&](uint64_t w) {
+            bool ok;
+            const uint64_t t = window_term_dw(bytes + w, ts, ok);
+            return ok ? t : kInvalidTerm;
+        },
+        0, 0, nw, uterms, hashes, ts, seeds, &lcount);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t ell = lcount;
+        const uint32_t nch = ell ? (ell + chunk - 1) / chunk : 0u;
+        const uint64_t thr = ((uint64_t)k_num * ell + k_den - 1) / k_den;
+        QInfo q;
+        q.hbase = 0;
+        q.ell = ell;
+        q.nch = nch;
+        q.pbase = nch > 1 ? (slot ? slot[0] : 0u) : 0xFFFFFFFFu;
+        q.thr = thr > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)thr;
+        nterms[0] = ell;
+        qinfo[0] = q;
+        qcount[0] = 0;
+        qorder[0] = 0;
+        chunk_prefix[0] = 0;
+        chunk_prefix[1] = nch;
+        *total_items = (uint64_t)nch * n_slices;
+        *work_counter = 0;
+        *cand_counter = 0;
+        *flags = (uint64_t)ell > ell_limit ? 1u : 0u;
+    }
+}
+
 // ---- ordering of the hits ------------------------------------------------------------------
 
 __global__ __launch_bounds__(1024) void group_scan_kernel(const uint32_t *qcount, uint32_t n,
@@ -453,21 +520,12 @@ __device__ __forceinline__ uint32_t count_greater(const uint64_t *b, uint32_t n,
     return lo;
 }
 
-// one workgroup per query: bitonic sort of runs of kSortRun keys in LDS, then
-// merge passes (every key finds its place by binary search; keys are distinct)
-__global__ __launch_bounds__(1024) void segsort_kernel(uint64_t *seg_a, uint64_t *seg_b,
-                                                       const unsigned long long *n_cand,
-                                                       uint64_t cap, const uint32_t *qstart,
-                                                       const uint32_t *out_start,
-                                                       const uint32_t *out_n, uint32_t *out_id,
-                                                       uint32_t *out_score)
+// One workgroup sorts n distinct keys descending: bitonic sort of runs of
+// kSortRun keys in LDS (s), then merge passes between src and dst (every key
+// finds its place by binary search).  Returns where the sorted keys are.
+__device__ __forceinline__ uint64_t *sort_desc(uint64_t *src, uint64_t *dst, uint32_t n, uint64_t *s)
 {
-    __shared__ uint64_t s[kSortRun];
-    if (*n_cand > cap) return;
-    const uint32_t q = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-    const uint32_t beg = qstart[q], n = qstart[q + 1] - beg;
-    if (n == 0) return;
-    uint64_t *src = seg_a + beg, *dst = seg_b + beg;
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
     for (uint32_t r0 = 0; r0 < n; r0 += kSortRun) {
         const uint32_t rn = min(kSortRun, n - r0);
         if (rn < 2) break;   // a run of one is sorted (only the last run can be short)
@@ -505,11 +563,57 @@ __global__ __launch_bounds__(1024) void segsort_kernel(uint64_t *seg_a, uint64_t
         __syncthreads();
         uint64_t *t = src; src = dst; dst = t;
     }
+    return src;
+}
+
+// one workgroup per query: its segment of candidates sorted, the first
+// out_n[q] written out
+__global__ __launch_bounds__(1024) void segsort_kernel(uint64_t *seg_a, uint64_t *seg_b,
+                                                       const unsigned long long *n_cand,
+                                                       uint64_t cap, const uint32_t *qstart,
+                                                       const uint32_t *out_start,
+                                                       const uint32_t *out_n, uint32_t *out_id,
+                                                       uint32_t *out_score)
+{
+    __shared__ uint64_t s[kSortRun];
+    if (*n_cand > cap) return;
+    const uint32_t q = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t beg = qstart[q], n = qstart[q + 1] - beg;
+    if (n == 0) return;
+    const uint64_t *src = sort_desc(seg_a + beg, seg_b + beg, n, s);
     const uint32_t o = out_start[q], k = out_n[q];
     for (uint32_t i = tid; i < k; i += nt) {
         const uint64_t v = src[i];
         out_id[o + i] = ~(uint32_t)v;
         out_score[o + i] = (uint32_t)(v >> 32);
+    }
+}
+
+// The hits of a batch of one query: every candidate is the query's, so they
+// are sorted where the gather wrote them (no grouping).  Writes the result
+// head's out_start[0..1] and out_n[0] as the grouping kernels would.
+__global__ __launch_bounds__(1024) void sort_one_kernel(uint64_t *cand_key, uint64_t *tmp,
+                                                        const unsigned long long *n_cand,
+                                                        uint64_t cap, uint32_t topk,
+                                                        uint32_t *out_start, uint32_t *out_n,
+                                                        uint32_t *out_id, uint32_t *out_score)
+{
+    __shared__ uint64_t s[kSortRun];
+    const unsigned long long nc = *n_cand;
+    if (nc > cap) return;   // overflow: the host enlarges the buffers and reruns
+    const uint32_t n = (uint32_t)nc, tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t k = topk ? min(n, topk) : n;
+    if (tid == 0) {
+        out_start[0] = 0;
+        out_start[1] = k;
+        out_n[0] = k;
+    }
+    if (n == 0) return;
+    const uint64_t *src = sort_desc(cand_key, tmp, n, s);
+    for (uint32_t i = tid; i < k; i += nt) {
+        const uint64_t v = src[i];
+        out_id[i] = ~(uint32_t)v;
+        out_score[i] = (uint32_t)(v >> 32);
     }
 }
 
@@ -768,6 +872,38 @@ hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, const uint
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, nterms, wbase, slot, n_queries, chunk,
                        n_slices, k_num, k_den, ell_limit, qinfo, qorder, chunk_prefix, total_items,
                        work_counter, cand_counter, qcount, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_front_one(const uint8_t *bytes, const uint64_t *wbase, uint64_t max_windows,
+                            const uint32_t *slot, uint64_t *uterms, uint64_t *hashes,
+                            uint32_t *nterms, TermSpec ts, Seeds seeds, uint32_t chunk,
+                            uint32_t n_slices, uint32_t k_num, uint32_t k_den, uint64_t ell_limit,
+                            QInfo *qinfo, uint32_t *qorder, uint32_t *chunk_prefix,
+                            uint64_t *total_items, unsigned long long *work_counter,
+                            unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags,
+                            hipStream_t st)
+{
+    if (table_cap(max_windows) > kLdsTableSlots) return hipErrorInvalidValue;
+    if (dedup_small_table(max_windows))
+        hipLaunchKernelGGL((front_one_kernel<kLdsTableSlots / 2, 256>), dim3(1), dim3(256), 0, st, bytes,
+                           wbase, slot, uterms, hashes, nterms, ts, seeds, chunk, n_slices, k_num, k_den,
+                           ell_limit, qinfo, qorder, chunk_prefix, total_items, work_counter,
+                           cand_counter, qcount, flags);
+    else
+        hipLaunchKernelGGL((front_one_kernel<kLdsTableSlots, 1024>), dim3(1), dim3(1024), 0, st, bytes,
+                           wbase, slot, uterms, hashes, nterms, ts, seeds, chunk, n_slices, k_num, k_den,
+                           ell_limit, qinfo, qorder, chunk_prefix, total_items, work_counter,
+                           cand_counter, qcount, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_one(uint64_t *cand_key, uint64_t *tmp, const unsigned long long *n_cand,
+                           uint64_t cap, uint32_t topk, uint32_t *out_start, uint32_t *out_n,
+                           uint32_t *out_id, uint32_t *out_score, hipStream_t st)
+{
+    hipLaunchKernelGGL(sort_one_kernel, dim3(1), dim3(1024), 0, st, cand_key, tmp, n_cand, cap, topk,
+                       out_start, out_n, out_id, out_score);
     return hipGetLastError();
 }
 

@@ -303,17 +303,21 @@ static cobs_status gather_streamed(cobs_index *ix, Workspace &ws, GatherArgs ga,
 
 // ---- single short queries: captured launch sequences ------------------------------
 
-// A batch of one query of at most kGraphMaxWindows windows (dedup in LDS)
-// runs its whole launch sequence -- extract, dedup, plan, gather, hit
-// ordering and the copy of the result head with the first kGraphInlineHits
-// hits -- as one hipGraph, captured once per workspace and launch-shape
-// class and replayed.  The class rounds the windows up to a power of two:
-// the extract grid and the gather grid cover the class's largest query, the
-// kernels read the query's real extent from the uploaded metadata, and the
-// term chunk is the class's, so a replay needs no parameter updates.  Results
-// do not depend on the chunk or the grid.  Only the metadata and query
-// bytes are copied in before the replay.
-constexpr uint64_t kGraphMaxWindows = 8192;
+// A batch of one query of at most kGraphMaxWindows windows
+// runs its whole launch sequence -- terms, set and plan in one workgroup,
+// the gather, the hits sorted in one workgroup, and the copy of the result
+// head with the first kGraphInlineHits hits -- as one hipGraph, captured
+// once per workspace and launch-shape class and replayed.  The class rounds
+// the windows up to a power of two: the LDS set and the gather grid cover the
+// class's largest query, the first kernel reads the query's real extent from
+// the uploaded metadata, and the term chunk is the class's, so a replay
+// needs no parameter updates.  Results do not depend on the chunk or the
+// grid.  Only the metadata and query bytes are copied in before the replay.
+// Up to 2,048 windows the three kernels win (1 kbp: 0.102 against 0.107 ms
+// end to end, 100 bp: 0.078 against 0.091); at 5 kbp one workgroup computing
+// every term is slower than the extract kernel spread over the device
+// (0.210 against 0.179 ms), so longer queries keep the general pipeline.
+constexpr uint64_t kGraphMaxWindows = 2048;
 constexpr uint32_t kGraphInlineHits = 512;
 
 static bool graph_eligible(const cobs_index *ix, const Workspace &ws, const BatchSpec &b,
@@ -423,8 +427,6 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
             ws.graphs_broken = true;
             return COBS_OK;
         }
-        BatchPlan cp = pl;
-        cp.W = wclass;   // grid bound; the kernels stop at the query's real windows
         GatherArgs ga{};
         ga.matrix = ix->d_matrix;
         ga.slices = ix->d_slices;
@@ -449,19 +451,19 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
         ga.topk = b.topk;
         ga.n_docs = ix->n_docs;
         ga.slice_major = order == COBS_ORDER_SLICES ? 1u : 0u;
-        hipError_t e = launch_front(ix, cp, mp, dmeta + meta, ws.terms.as<uint64_t>(), ws.table.as<uint64_t>(),
-                                    ws.uterms.as<uint64_t>(), ws.hashes.as<uint64_t>(), d_nterms, cs);
-        if (e == hipSuccess)
-            e = launch_plan(d_nterms, mp.wbase, mp.slot, 1, chunk, n_slices, b.k_num, b.k_den, ell_limit,
-                            ws.qinfo.as<QInfo>(), ws.qorder.as<uint32_t>(), ws.chunk_prefix.as<uint32_t>(),
-                            &dsc->total_items, &dsc->work_counter, &dsc->cand_counter, ws.qcount.as<uint32_t>(),
-                            &dsc->flags, cs);
+        // three kernels: terms, set and plan in one workgroup; the gather; the
+        // hits sorted where the gather wrote them
+        hipError_t e = launch_front_one(dmeta + meta, mp.wbase, wclass, mp.slot, ws.uterms.as<uint64_t>(),
+                                        ws.hashes.as<uint64_t>(), d_nterms, term_spec(ix->prm), ix->seeds,
+                                        chunk, n_slices, b.k_num, b.k_den, ell_limit, ws.qinfo.as<QInfo>(),
+                                        ws.qorder.as<uint32_t>(), ws.chunk_prefix.as<uint32_t>(),
+                                        &dsc->total_items, &dsc->work_counter, &dsc->cand_counter,
+                                        ws.qcount.as<uint32_t>(), &dsc->flags, cs);
         if (e == hipSuccess) e = launch_gather(ga, pl.planes, pl.unroll, grid, pl.packed, cs);
         if (e == hipSuccess)
-            e = launch_group_sort(ws.cand_key.as<uint64_t>(), ws.cand_q.as<uint32_t>(), &dsc->cand_counter,
-                                  ws.cand_cap, 1, b.topk, ws.qcount.as<uint32_t>(), ws.gstart.as<uint32_t>(),
-                                  ws.gcursor.as<uint32_t>(), ws.seg_a.as<uint64_t>(), ws.seg_b.as<uint64_t>(),
-                                  d_out_start, d_out_n, ws.out_id.as<uint32_t>(), ws.out_score.as<uint32_t>(), cs);
+            e = launch_sort_one(ws.cand_key.as<uint64_t>(), ws.seg_a.as<uint64_t>(), &dsc->cand_counter,
+                                ws.cand_cap, b.topk, d_out_start, d_out_n, ws.out_id.as<uint32_t>(),
+                                ws.out_score.as<uint32_t>(), cs);
         if (e == hipSuccess) e = hipMemcpyAsync(hs, ws.head.p, head_bytes, hipMemcpyDeviceToHost, cs);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hs + inline_off, ws.out_id.p, 4 * (size_t)kGraphInlineHits, hipMemcpyDeviceToHost, cs);

@@ -251,3 +251,23 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_bench_cpu_baseline_on_a_whole_block():
+    # the CPU-baseline leg on a small compact plan: a whole block of 1,024
+    # documents as sub-indexes at the block's row count, the per-lookup and
+    # per-document model, and its check on the half block
+    sys.path.insert(0, ROOT)
+    import bench
+    import oracle
+    from dataclasses import replace
+    w = replace(synth.CONFIGS[3].scaled(40), B=1024)
+    lens = synth.doc_lengths(w).astype(np.int64)
+    n_terms = lens - 30           # the exact counts do not matter for the timing
+    order = np.lexsort((np.arange(w.n_docs), n_terms))
+    qs = synth.dna_queries(w, n=20)
+    r = bench.cpu_baseline_block(w, synth, oracle, qs, order, n_terms, 1.5, 2)
+    assert r["kind"] == "oracle" and r["cores"] == 2
+    assert r["value"] > 0 and r["value_1_thread"] > 0
+    assert r["ns_per_lookup"] > 0 and r["ns_per_lookup_document"] > 0
+    assert "block 0 of the compact plan" in r["sample"] and "1025 columns" in r["sample"]
