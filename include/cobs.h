@@ -324,7 +324,7 @@ cobs_status cobs_query_scores(cobs_index *ix, const uint8_t *bytes,
  * carved out of one fixed scratch array of 64 MiB that the library holds on
  * each device it runs on until the process ends; a batch that needs more
  * fails with EBUDGET (8 (2 + h) bytes per window, up to 32 more per window
- * of queries longer than 8,192 windows, and 4 bytes per document for every
+ * of queries longer than 12,288 windows, and 4 bytes per document for every
  * query longer than one work item).
  *  bytes     device memory: query i is bytes[q_off[i] .. q_off[i+1])
  *  q_off     host array [n_queries + 1], non-decreasing

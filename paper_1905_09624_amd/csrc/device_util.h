@@ -75,5 +75,24 @@ __device__ __forceinline__ uint32_t bsearch_le(const T *a, uint32_t n, uint64_t 
     return lo;
 }
 
+// bsearch_le for a value v uniform over the wavefront (every lane active): 64
+// probes per step, so three steps cover 10^5 entries.
+template <typename T>
+__device__ __forceinline__ uint32_t wave_search_le(const T *a, uint32_t n, uint64_t v)
+{
+    const uint32_t lane = lane_id();
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + 63) / 64;
+        const uint32_t i = lo + lane * step;
+        const uint64_t m = __ballot(i < hi && (uint64_t)a[i] <= v);   // lanes 0 .. k-1
+        const uint32_t k = 64u - (uint32_t)__builtin_clzll(m);
+        const uint32_t nhi = lo + k * step;
+        lo += (k - 1) * step;
+        if (nhi < hi) hi = nhi;
+    }
+    return lo;
+}
+
 }  // namespace
 }  // namespace cobs

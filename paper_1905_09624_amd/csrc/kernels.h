@@ -11,6 +11,11 @@ constexpr int kMaxHashes = 8;
 constexpr uint64_t kInvalidTerm = ~0ull;   // DNA window with a non-ACGT byte
 constexpr uint32_t kSliceBytes = 1024;     // one wavefront: 64 lanes x 16 bytes
 constexpr uint32_t kLdsTableSlots = 16384; // largest dedup table held in LDS (128 KiB)
+constexpr uint32_t kLdsTinySlots = 2048;   // 16 KiB tables: many workgroups per CU
+// Queries of up to kLdsMaxWindows windows dedup in LDS: a table of twice
+// their windows rounded up to a power of two, at most kLdsTableSlots (load
+// at most 0.75); longer queries use a table in device memory.
+constexpr uint64_t kLdsMaxWindows = 12288;
 constexpr uint32_t kSortRun = 2048;        // candidates sorted in LDS per run
 constexpr uint32_t kSliceDocs = 8192;      // documents per slice (score buffer stride)
 constexpr uint32_t kDedupWindowsPerGroup = 16384; // windows per workgroup of a global-table query
@@ -109,18 +114,20 @@ hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const ui
 // a2+a3: per-query set of terms (hash-set dedup) and the h hashes of each
 // distinct term; nterms[i] = l of query i (zeroed by launch_extract).  A query
 // whose set fits in LDS is one workgroup with an LDS table: lds_q lists the
-// n_small queries with dedup_small_table(windows), then n_large others.  A
+// n_tiny queries with dedup_tiny_table(windows), then n_small others with
+// dedup_small_table(windows), then n_large others.  A
 // larger one (listed in g_q) has dedup_table_slots(windows) global slots at
 // table + tbase[i] (cleared here) and dedup_groups(windows) workgroups;
 // gprefix[j]: first workgroup of g_q[j], g_groups = gprefix[n_g];
 // table_slots: total global slots.
 hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint64_t *tbase,
-                        const uint32_t *lds_q, uint32_t n_small, uint32_t n_large,
+                        const uint32_t *lds_q, uint32_t n_tiny, uint32_t n_small, uint32_t n_large,
                         const uint32_t *g_q, const uint32_t *gprefix, uint32_t n_g,
                         uint32_t g_groups, uint64_t *table, uint64_t table_slots,
                         uint64_t *uterms, uint64_t *hashes, uint32_t *nterms, TermSpec ts,
                         Seeds seeds, hipStream_t st);
-bool dedup_small_table(uint64_t windows);      // LDS table of kLdsTableSlots / 2 or fewer
+bool dedup_tiny_table(uint64_t windows);       // LDS table of kLdsTinySlots slots or fewer
+bool dedup_small_table(uint64_t windows);      // LDS table of kLdsTableSlots / 2 slots or fewer
 uint64_t dedup_table_cap(uint64_t windows);    // hash-set capacity for a query (power of 2)
 uint64_t dedup_table_slots(uint64_t windows);  // global slots (0: LDS table)
 uint32_t dedup_groups(uint64_t windows);       // workgroups of the query
@@ -160,8 +167,7 @@ hipError_t launch_group_sort(const uint64_t *cand_key, const uint32_t *cand_q,
                              uint32_t *out_n, uint32_t *out_id, uint32_t *out_score,
                              hipStream_t st);
 
-// A batch of one query of at most max_windows <= kLdsTableSlots / 2
-// windows: a1-a3 and the plan in one workgroup (terms straight into an LDS
+// A batch of one query of at most max_windows <= kLdsMaxWindows windows: a1-a3 and the plan in one workgroup (terms straight into an LDS
 // set); the same outputs as launch_extract + launch_dedup + launch_plan with
 // n_queries = 1.  bytes: the query, 4-byte aligned, 64 readable bytes after.
 hipError_t launch_front_one(const uint8_t *bytes, const uint64_t *wbase, uint64_t max_windows,

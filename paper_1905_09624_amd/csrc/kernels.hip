@@ -106,36 +106,104 @@ __host__ __device__ __forceinline__ uint64_t table_cap(uint64_t n)
 
 // ---- a1: term extraction ------------------------------------------------------
 
-// Each wavefront takes tiles of 64 x per_lane consecutive windows
-// (consecutive lanes, consecutive windows: coalesced term writes); the query
-// of a tile's first window is found by one binary search, later windows
-// advance from it.  per_lane is 16 for large batches and shrinks for small
-// ones, so that a short query still spreads over several wavefronts.
+// Each lane takes per_lane consecutive windows (a wavefront 64 x per_lane).
+// A lane's windows of one query span at most per_lane + q - 1 bytes; it
+// loads them as 13 aligned dwords (the batch's byte buffer has 64 bytes of
+// slack past its end, so this never reads outside it) and rolls them in one
+// by one: DNA shifts the forward packing left and the reverse complement
+// right, text shifts the little-endian word right, and a count of the valid
+// bases ending at the current byte marks windows with a non-ACGT byte.  A
+// lane whose windows cross into another query does this once per query.
+// The terms go through the wavefront's LDS tile (rows padded to 17 words)
+// so that the stores to terms[] are coalesced.  per_lane is a power of two,
+// 16 for large batches and smaller for small ones, so that a short query
+// still spreads over several wavefronts.
 constexpr uint32_t kExtractPerLane = 16;
+constexpr uint32_t kExtractPad = kExtractPerLane + 1;
+constexpr uint32_t kExtractDwords = 13;   // 48 bytes after realignment >= kExtractPerLane + 31 - 1
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ __launch_bounds__(256) void extract_kernel(const uint8_t *bytes, const uint64_t *qstart,
                                                       const uint64_t *wbase, uint32_t n, uint64_t W,
-                                                      uint32_t per_lane, TermSpec ts, uint64_t *terms,
-                                                      uint32_t *nterms)
+                                                      uint32_t lg_per_lane, TermSpec ts,
+                                                      uint64_t *terms, uint32_t *nterms)
 {
+    __shared__ uint64_t stage[4][64 * kExtractPad];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         nterms[i] = 0;
-    W = min(W, wbase[n]);   // W may bound the windows from above (a replayed launch)
+    W = min(W, wbase[n]);   // W may bound the windows from above
     const uint32_t lane = lane_id();
+    const uint32_t per_lane = 1u << lg_per_lane;
     const uint64_t tile = 64ull * per_lane;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t waves = stride >> 6;
+    uint64_t *sg = stage[threadIdx.x >> 6] + lane * kExtractPad;
+    const uint32_t q = ts.q;
+    const bool text = ts.kind == 1;
+    const uint64_t mask = q >= 32 ? ~0ull : (1ull << (2 * q)) - 1;
+    const uint32_t top = text ? 8 * (q - 1) : 2 * (q - 1);
     for (uint64_t t0 = wave * tile; t0 < W; t0 += waves * tile) {
-        uint32_t qi = bsearch_le(wbase, n, t0);
-        for (uint32_t i = 0; i < per_lane; ++i) {
-            const uint64_t w = t0 + (uint64_t)i * 64 + lane;
-            if (w >= W) break;
-            while (w >= wbase[qi + 1]) ++qi;
-            bool ok;
-            const uint64_t t = window_term_dw(bytes + qstart[qi] + (w - wbase[qi]), ts, ok);
-            terms[w] = ok ? t : kInvalidTerm;
+        const uint64_t m = min(tile, W - t0);
+        // queries of the tile's first and last windows; the lanes search between
+        const uint32_t qa = wave_search_le(wbase, n, t0);
+        const uint32_t qb = wave_search_le(wbase, n, t0 + m - 1);
+        wave_lds_sync();   // the previous tile's reads are done
+        const uint64_t wb = t0 + (uint64_t)lane * per_lane;
+        const uint64_t we = min(t0 + m, wb + per_lane);
+        if (wb < we) {
+            uint32_t qi = qa + bsearch_le(wbase + qa, qb - qa + 1, wb);
+            for (uint64_t w0 = wb; w0 < we;) {
+                while (w0 >= wbase[qi + 1]) ++qi;
+                const uint64_t w1 = min(we, wbase[qi + 1]);
+                const uint32_t nwin = (uint32_t)(w1 - w0), span = nwin + q - 1;
+                const uint8_t *s = bytes + qstart[qi] + (w0 - wbase[qi]);
+                const uint32_t o = (uint32_t)((uintptr_t)s & 3u);
+                const uint32_t *wp = (const uint32_t *)(s - o);
+                uint32_t d[kExtractDwords];
+#pragma unroll
+                for (uint32_t k = 0; k < kExtractDwords; ++k) d[k] = wp[k];
+                const uint32_t slot0 = (uint32_t)(w0 - wb);
+                uint64_t fwd = 0, rc = 0;
+                uint32_t run = 0;
+#pragma unroll
+                for (uint32_t k = 0; k + 1 < kExtractDwords; ++k) {
+                    if (4 * k >= span) break;
+                    const uint32_t a = __builtin_amdgcn_alignbyte(d[k + 1], d[k], o);
+#pragma unroll
+                    for (uint32_t b4 = 0; b4 < 4; ++b4) {
+                        const uint32_t j = 4 * k + b4;   // byte j ends window j - (q - 1)
+                        const uint32_t u = (a >> (8 * b4)) & 0xFFu;
+                        if (text) {
+                            fwd = (fwd >> 8) | ((uint64_t)u << top);
+                        } else {
+                            const uint32_t v = u & 0xDFu;
+                            const bool valid = (v == 'A') | (v == 'C') | (v == 'G') | (v == 'T');
+                            const uint32_t c = ((v >> 1) ^ (v >> 2)) & 3u;
+                            fwd = ((fwd << 2) | c) & mask;
+                            rc = (rc >> 2) | ((uint64_t)(3u - c) << top);
+                            run = valid ? run + 1 : 0u;
+                        }
+                        if (j + 1 >= q && j < span) {
+                            uint64_t t = fwd;
+                            if (!text && ts.canonical && rc < t) t = rc;
+                            sg[slot0 + j + 1 - q] = (text || run >= q) ? t : kInvalidTerm;
+                        }
+                    }
+                }
+                w0 = w1;
+            }
         }
+        wave_lds_sync();   // the tile's terms are in LDS
+        const uint64_t *st = stage[threadIdx.x >> 6];
+        for (uint32_t j = lane; j < m; j += 64)
+            terms[t0 + j] = st[(j >> lg_per_lane) * kExtractPad + (j & (per_lane - 1))];
     }
 }
 
@@ -176,19 +244,19 @@ __device__ __forceinline__ void dedup_windows(uint64_t *table, uint64_t cap, uin
                                               TermSpec ts, const Seeds &seeds, uint32_t *count)
 {
     const uint32_t lane = lane_id();
+    // the next round's term is loaded before this round's inserts
+    uint64_t next = b + threadIdx.x < e ? term_at(b + threadIdx.x) : 0;
     for (uint64_t base = b; base < e; base += blockDim.x) {
         const uint64_t w = base + threadIdx.x;
         bool fresh = false;
-        uint64_t t = 0, hs[kMaxHashes];
-        if (w < e) {
-            t = term_at(w);
-            if (ts.kind == 1 || t != kInvalidTerm) {
+        uint64_t t = next, hs[kMaxHashes];
+        if (w + blockDim.x < e) next = term_at(w + blockDim.x);
+        if (w < e && (ts.kind == 1 || t != kInvalidTerm)) {
 #pragma unroll
-                for (int i = 0; i < kMaxHashes; ++i)
-                    if (i < (int)ts.h) hs[i] = mix64(t ^ seeds.s[i]);
-                fresh = t == kEmpty ? cas64<kScope>(flag, kEmpty, 0) == kEmpty
-                                    : set_insert<kScope>(table, cap, t, hs[0] & (cap - 1));
-            }
+            for (int i = 0; i < kMaxHashes; ++i)
+                if (i < (int)ts.h) hs[i] = mix64(t ^ seeds.s[i]);
+            fresh = t == kEmpty ? cas64<kScope>(flag, kEmpty, 0) == kEmpty
+                                : set_insert<kScope>(table, cap, t, hs[0] & (cap - 1));
         }
         const uint64_t m = __ballot(fresh);
         if (m == 0) continue;
@@ -218,8 +286,9 @@ __device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint6
 }
 
 // One workgroup per query whose set fits in kSlots LDS slots (lds_q: those
-// queries): 64 KiB tables for up to 4,096 windows, 128 KiB tables (one
-// workgroup of 1,024 threads per CU) for up to 8,192.
+// queries): 16 KiB tables for up to 1,024 windows, 64 KiB tables for up to
+// 4,096, 128 KiB tables (one workgroup of 1,024 threads per CU) for up to
+// 12,288 (at most 3/4 full).
 template <uint32_t kSlots, int kThreads>
 __global__ __launch_bounds__(kThreads) void dedup_lds_kernel(const uint64_t *terms, const uint64_t *wbase,
                                                              const uint32_t *lds_q, uint64_t *uterms,
@@ -231,12 +300,12 @@ __global__ __launch_bounds__(kThreads) void dedup_lds_kernel(const uint64_t *ter
     __shared__ uint32_t lcount;
     const uint32_t qi = lds_q[blockIdx.x];
     const uint64_t w0 = wbase[qi], nw = wbase[qi + 1] - w0;
-    const uint64_t cap = table_cap(nw);
+    const uint64_t cap = table_cap(nw) < kSlots ? table_cap(nw) : kSlots;
     if (threadIdx.x == 0) { lcount = 0; lflag = kEmpty; }
     for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) ltable[s] = kEmpty;
     __syncthreads();
-    dedup_range<__HIP_MEMORY_SCOPE_WORKGROUP>(ltable, cap, &lflag, terms, w0, 0, nw, uterms, hashes,
-                                              ts, seeds, &lcount);
+    dedup_range<__HIP_MEMORY_SCOPE_WORKGROUP>(ltable, cap, &lflag, terms, w0, 0, nw, uterms,
+                                                 hashes, ts, seeds, &lcount);
     __syncthreads();
     if (threadIdx.x == 0) nterms[qi] = lcount;
 }
@@ -265,16 +334,16 @@ __global__ __launch_bounds__(1024) void dedup_global_kernel(const uint64_t *term
     if (nw <= kDedupWindowsPerGroup) {
         if (threadIdx.x == 0) lcount = 0;
         __syncthreads();
-        dedup_range<__HIP_MEMORY_SCOPE_WORKGROUP>(table, cap, table + cap, terms, w0, 0, nw, uterms,
-                                                  hashes, ts, seeds, &lcount);
+        dedup_range<__HIP_MEMORY_SCOPE_WORKGROUP>(table, cap, table + cap, terms, w0, 0, nw,
+                                                     uterms, hashes, ts, seeds, &lcount);
         __syncthreads();
         if (threadIdx.x == 0) nterms[qi] = lcount;
         return;
     }
     const uint64_t b = (uint64_t)part * kDedupWindowsPerGroup;
     const uint64_t e = min(nw, b + kDedupWindowsPerGroup);
-    dedup_range<__HIP_MEMORY_SCOPE_AGENT>(table, cap, table + cap, terms, w0, b, e, uterms, hashes, ts,
-                                          seeds, &nterms[qi]);
+    dedup_range<__HIP_MEMORY_SCOPE_AGENT>(table, cap, table + cap, terms, w0, b, e, uterms, hashes,
+                                             ts, seeds, &nterms[qi]);
 }
 
 // ---- plan ------------------------------------------------------------------------------
@@ -394,7 +463,7 @@ __global__ __launch_bounds__(kThreads) void front_one_kernel(
     __shared__ uint64_t lflag;
     __shared__ uint32_t lcount;
     const uint64_t nw = wbase[1] - wbase[0];
-    const uint64_t cap = table_cap(nw);
+    const uint64_t cap = table_cap(nw) < kSlots ? table_cap(nw) : kSlots;
     if (threadIdx.x == 0) { lcount = 0; lflag = kEmpty; }
     for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) ltable[s] = kEmpty;
     __syncthreads();
@@ -816,29 +885,33 @@ hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const ui
                           uint32_t *nterms, hipStream_t st)
 {
     if (n_queries == 0) return hipSuccess;
-    // about 8192 wavefronts' worth of tiles, 1 to kExtractPerLane windows per lane
-    const uint32_t per_lane = (uint32_t)std::min<uint64_t>(
-        kExtractPerLane, std::max<uint64_t>(1, W / (64ull * 8192)));
-    const uint64_t tiles = (W + 64ull * per_lane - 1) / (64ull * per_lane);
+    // about 8192 wavefronts' worth of tiles, 1 to kExtractPerLane windows per
+    // lane (a power of two)
+    uint32_t lg = 0;
+    while ((2u << lg) <= kExtractPerLane && (64ull * 8192) << (lg + 1) <= W) ++lg;
+    const uint64_t tiles = (W + (64ull << lg) - 1) / (64ull << lg);
     hipLaunchKernelGGL(extract_kernel,
                        dim3(grid_for(std::max<uint64_t>(tiles * 64, n_queries), 256)), dim3(256), 0,
-                       st, bytes, qstart, wbase, n_queries, W, per_lane, ts, terms, nterms);
+                       st, bytes, qstart, wbase, n_queries, W, lg, ts, terms, nterms);
     return hipGetLastError();
 }
 
 hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint64_t *tbase,
-                        const uint32_t *lds_q, uint32_t n_small, uint32_t n_large,
+                        const uint32_t *lds_q, uint32_t n_tiny, uint32_t n_small, uint32_t n_large,
                         const uint32_t *g_q, const uint32_t *gprefix, uint32_t n_g,
                         uint32_t g_groups, uint64_t *table, uint64_t table_slots,
                         uint64_t *uterms, uint64_t *hashes, uint32_t *nterms, TermSpec ts,
                         Seeds seeds, hipStream_t st)
 {
+    if (n_tiny)
+        hipLaunchKernelGGL((dedup_lds_kernel<kLdsTinySlots, 256>), dim3(n_tiny), dim3(256), 0, st,
+                           terms, wbase, lds_q, uterms, hashes, nterms, ts, seeds);
     if (n_small)
         hipLaunchKernelGGL((dedup_lds_kernel<kLdsTableSlots / 2, 256>), dim3(n_small), dim3(256), 0, st,
-                           terms, wbase, lds_q, uterms, hashes, nterms, ts, seeds);
+                           terms, wbase, lds_q + n_tiny, uterms, hashes, nterms, ts, seeds);
     if (n_large)
         hipLaunchKernelGGL((dedup_lds_kernel<kLdsTableSlots, 1024>), dim3(n_large), dim3(1024), 0, st,
-                           terms, wbase, lds_q + n_small, uterms, hashes, nterms, ts, seeds);
+                           terms, wbase, lds_q + n_tiny + n_small, uterms, hashes, nterms, ts, seeds);
     if (n_g) {
         hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(table_slots, 256)), dim3(256), 0, st,
                            table, table_slots, kEmpty);
@@ -850,15 +923,16 @@ hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint
 
 uint64_t dedup_table_slots(uint64_t windows)
 {
-    const uint64_t cap = table_cap(windows);
-    return cap <= kLdsTableSlots ? 0 : cap + 1;
+    return windows <= kLdsMaxWindows ? 0 : table_cap(windows) + 1;
 }
+
+bool dedup_tiny_table(uint64_t windows) { return table_cap(windows) <= kLdsTinySlots; }
 
 bool dedup_small_table(uint64_t windows) { return table_cap(windows) <= kLdsTableSlots / 2; }
 
 uint32_t dedup_groups(uint64_t windows)
 {
-    if (table_cap(windows) <= kLdsTableSlots) return 1;
+    if (windows <= kLdsMaxWindows) return 1;
     return (uint32_t)std::max<uint64_t>(1, (windows + kDedupWindowsPerGroup - 1) / kDedupWindowsPerGroup);
 }
 
@@ -884,7 +958,7 @@ hipError_t launch_front_one(const uint8_t *bytes, const uint64_t *wbase, uint64_
                             unsigned long long *cand_counter, uint32_t *qcount, uint32_t *flags,
                             hipStream_t st)
 {
-    if (table_cap(max_windows) > kLdsTableSlots) return hipErrorInvalidValue;
+    if (max_windows > kLdsMaxWindows) return hipErrorInvalidValue;
     if (dedup_small_table(max_windows))
         hipLaunchKernelGGL((front_one_kernel<kLdsTableSlots / 2, 256>), dim3(1), dim3(256), 0, st, bytes,
                            wbase, slot, uterms, hashes, nterms, ts, seeds, chunk, n_slices, k_num, k_den,

@@ -95,9 +95,9 @@ struct BatchPlan {
     uint64_t byte0 = 0, nbytes = 0, W = 0, maxw = 0, tslots = 0, groups = 0, pslots = 0;
     std::vector<uint64_t> hv;            // qstart[n] | wbase[n + 1]
     std::vector<uint64_t> tb;            // first global dedup slot of each query
-    std::vector<uint32_t> lds_q;         // LDS-table queries: n_small small ones, then large ones
+    std::vector<uint32_t> lds_q;         // LDS-table queries: n_tiny, n_small, then n_large ones
     std::vector<uint32_t> g_q, gprefix;  // global-table queries; first workgroup of each, then the total
-    uint32_t n_small = 0, n_large = 0;
+    uint32_t n_tiny = 0, n_small = 0, n_large = 0;
     int planes = 0, unroll = 0, grid = 0;
     bool packed = false;
     bool in_place = false;               // offloaded index: rows read from host memory in place
@@ -137,7 +137,7 @@ cobs_status plan_batch(cobs_index *ix, const BatchSpec &b, BatchPlan &pl)
     // dedup work lists: queries with an LDS set; queries with a global table
     // and the first workgroup of each
     pl.tb.assign(n, 0);
-    std::vector<uint32_t> lds_large;
+    std::vector<uint32_t> lds_small, lds_large;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t nw = wbase[i + 1] - wbase[i];
         const uint64_t slots = dedup_table_slots(nw);
@@ -147,14 +147,18 @@ cobs_status plan_batch(cobs_index *ix, const BatchSpec &b, BatchPlan &pl)
             pl.g_q.push_back(i);
             pl.gprefix.push_back((uint32_t)pl.groups);
             pl.groups += dedup_groups(nw);
-        } else if (dedup_small_table(nw)) {
+        } else if (dedup_tiny_table(nw)) {
             pl.lds_q.push_back(i);
+        } else if (dedup_small_table(nw)) {
+            lds_small.push_back(i);
         } else {
             lds_large.push_back(i);
         }
     }
-    pl.n_small = (uint32_t)pl.lds_q.size();
+    pl.n_tiny = (uint32_t)pl.lds_q.size();
+    pl.n_small = (uint32_t)lds_small.size();
     pl.n_large = (uint32_t)lds_large.size();
+    pl.lds_q.insert(pl.lds_q.end(), lds_small.begin(), lds_small.end());
     pl.lds_q.insert(pl.lds_q.end(), lds_large.begin(), lds_large.end());
     if (pl.groups > 0x7FFFFFFFull) return set_error(COBS_EINVAL, "query batch too large");
     pl.gprefix.push_back((uint32_t)pl.groups);
@@ -250,7 +254,7 @@ hipError_t launch_front(const cobs_index *ix, const BatchPlan &pl, const MetaPtr
     const TermSpec ts = term_spec(ix->prm);
     hipError_t e = launch_extract(dbytes, mp.qstart, mp.wbase, pl.n, pl.W, ts, terms, nterms, st);
     if (e != hipSuccess) return e;
-    return launch_dedup(terms, mp.wbase, mp.tbase, mp.lds_q, pl.n_small, pl.n_large, mp.g_q,
+    return launch_dedup(terms, mp.wbase, mp.tbase, mp.lds_q, pl.n_tiny, pl.n_small, pl.n_large, mp.g_q,
                         mp.gprefix, (uint32_t)pl.g_q.size(), (uint32_t)pl.groups, table, pl.tslots,
                         uterms, hashes, nterms, ts, ix->seeds, st);
 }

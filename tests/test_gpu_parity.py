@@ -160,6 +160,36 @@ def test_bytes_terms_with_all_ones_term():
     assert gix.order()[1][0] == 3 + 8   # distinct 8-grams of the document
 
 
+@pytest.mark.parametrize("kind", ["dna", "bytes"])
+def test_terms_of_a_batch_of_millions_of_windows(kind):
+    # over 8.4 million windows in one batch: each lane of the extract kernel
+    # takes 16 consecutive windows, and many lanes hold the end of one query
+    # and the start of the next (queries of 0 to 40 bytes among long ones)
+    cobs = _cobs()
+    rng = np.random.default_rng(21)
+    if kind == "dna":
+        q, prm, doc = 31, cobs.make_params(0, 31, True, 1, 0.3, 0, 1), rand_dna(rng, 500)
+        alphabet = np.frombuffer(b"ACGTacgt" * 8 + b"N", np.uint8)
+        gen = lambda n: rng.choice(alphabet, n).tobytes()
+    else:
+        q, prm, doc = 8, cobs.make_params(1, 8, False, 3, 0.1, 0, 3), b"abcdefghijklmnop"
+        gen = lambda n: rng.integers(0, 256, n, dtype=np.uint8).tobytes()
+    d = oracle.Docs.from_lists([doc])
+    gix = cobs.Index.build(prm, d.bytes, d.str_off, d.doc_str)
+    qs, windows = [], 0
+    while windows < 9_000_000:
+        r = rng.random()
+        n = int(rng.integers(0, 41) if r < 0.4 else rng.integers(41, 300) if r < 0.7
+                else rng.integers(300, 60000))
+        qs.append(gen(n))
+        windows += max(n - q + 1, 0)
+    data, off = queries_of(qs)
+    got = gix.terms(data, off, q=q)
+    for i, s in enumerate(qs):
+        want = oracle.unique(oracle.terms(0 if kind == "dna" else 1, q, kind == "dna", s))
+        assert np.array_equal(np.sort(got[i]), want), (i, len(s))
+
+
 def test_index_from_fasta_files_with_many_reads(tmp_path):
     # documents read from FASTA files: every read is a string of its document
     # (no k-mer spans two reads); the index and hits equal the oracle's over
@@ -298,15 +328,16 @@ def test_edge_queries():
 
 
 def test_long_query_multi_chunk_and_global_table():
-    # > 8192 windows: dedup table in global memory (> 16384: several
-    # workgroups); 5,000-8,192 windows: the 128 KiB LDS table; > 1024 terms: several
-    # chunks merged by the last wavefront of each (query, slice)
+    # > 12,288 windows: dedup table in global memory (> 16384: several
+    # workgroups); 4,097-12,288 windows: the 128 KiB LDS table (12,000: load
+    # 0.73); > 1024 terms: several chunks merged by the last wavefront of
+    # each (query, slice)
     rng = np.random.default_rng(6)
     docs = oracle.Docs.from_lists([rand_dna(rng, 30000) for _ in range(12)])
     gix, oix = build_both(docs, 0, 31, True, 1, 0.3, 4, 2)
     d0 = docs.bytes[int(docs.str_off[0]):int(docs.str_off[1])].tobytes()
     qs = [d0[:20000] + rand_dna(rng, 30000), rand_dna(rng, 70000), d0, d0[:6000],
-          rand_dna(rng, 12000)]
+          rand_dna(rng, 12000), rand_dna(rng, 14000)]
     data, off = queries_of(qs)
     sc, l = gix.scores(data, off)
     for i, s in enumerate(qs):
