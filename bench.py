@@ -127,11 +127,13 @@ def committed_traffic(workload: str):
 
 
 def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, plain_n, streams,
-                  set_launch=None):
+                  set_launch=None, set_prune=None):
     """Served latency and throughput on the resident index: Poisson arrivals at
     each rate (open loop, native submitter), query lengths log-uniform in
     [31, 10^6] bp, half planted; beside it the plain path (one query per
-    launch, back to back) and one batch of the whole pool."""
+    launch, back to back) and one batch of the whole pool.  With set_prune,
+    the plain path and the server again with early exit of threshold queries
+    (same results)."""
     import numpy as np
     w5 = synth.CONFIGS[5]
     t0 = time.time()
@@ -143,19 +145,23 @@ def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, pl
            "rates": []}
     # plain path: closed loop, one query per launch
     sub = pool.subset(range(min(plain_n, pool_n)))
-    lat = []
-    nt_total = 0
-    for i in range(sub.n):
-        q = np.frombuffer(sub.get(i), np.uint8)
-        off = np.array([0, q.size], np.uint64)
-        t1 = time.perf_counter()
-        nt = ix.query_flat(q, off, k=k, mode=cobs.MODE_PLAIN)[0]
-        lat.append(time.perf_counter() - t1)
-        nt_total += int(nt.sum())
-    lat = np.array(lat)
-    plain = {"queries_per_s": sub.n / lat.sum(), "lookups_per_s": nt_total / lat.sum(),
-             "p50_ms": float(np.percentile(lat, 50) * 1e3),
-             "p99_ms": float(np.percentile(lat, 99) * 1e3), "queries": sub.n}
+
+    def closed_loop():
+        lat = []
+        nt_total = 0
+        for i in range(sub.n):
+            q = np.frombuffer(sub.get(i), np.uint8)
+            off = np.array([0, q.size], np.uint64)
+            t1 = time.perf_counter()
+            nt = ix.query_flat(q, off, k=k, mode=cobs.MODE_PLAIN)[0]
+            lat.append(time.perf_counter() - t1)
+            nt_total += int(nt.sum())
+        lat = np.array(lat)
+        return {"queries_per_s": sub.n / lat.sum(), "lookups_per_s": nt_total / lat.sum(),
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "queries": sub.n}
+
+    plain = closed_loop()
     out["plain_path"] = plain
     log(f"serving plain path: {plain}")
     # the whole pool as one batch (host bytes, as the server receives them)
@@ -193,6 +199,19 @@ def serve_measure(cobs, synth, torch, ix, rates, pool_n, per_rate_s, max_req, pl
             set_launch(cobs.LAUNCH_AUTO)
         out["rates"].append(rec)
         log(f"serving at {rate} q/s: {rec}")
+    if set_prune is not None:
+        set_prune(True)
+        pp = closed_loop()
+        out["pruned"] = {"plain_path": pp, "rates": []}
+        log(f"serving plain path, pruned: {pp}")
+        for rate in rates:
+            n = int(min(max_req, max(rate * per_rate_s, 200)))
+            rec = {"rate_qps": rate, **replay(n, rate, num_streams=streams)}
+            rec["vs_plain_throughput"] = rec["queries_per_s"] / plain["queries_per_s"]
+            rec["vs_plain_pruned_throughput"] = rec["queries_per_s"] / pp["queries_per_s"]
+            out["pruned"]["rates"].append(rec)
+            log(f"serving at {rate} q/s, pruned: {rec}")
+        set_prune(False)
     return out
 
 
@@ -464,6 +483,29 @@ def main():
         torch.cuda.synchronize()
         topk_ms = (time.perf_counter() - t1) / 2 * 1e3
 
+    # early exit (cobs_prune): the same threshold step with pruning on, whose
+    # hits must equal the unpruned step's; lookups counted the same way
+    ix.set_tuning(tuning["unroll"], tuning["chunk"], tuning["order"], prune=cobs.PRUNE_ON)
+    _, _, pids, pscores = ix.query_flat(qdev, q_off, k=k, topk=0)
+    cobs.profile(True)
+    cobs.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    psteps = max(args.steps // 2, 2)
+    for _ in range(psteps):
+        ix.query_flat(qdev, q_off, k=k, topk=0)
+    torch.cuda.synchronize()
+    pdt = (time.perf_counter() - t1) / psteps
+    pprof = cobs.profile_read(reset=True)
+    cobs.profile(False)
+    ix.set_tuning(tuning["unroll"], tuning["chunk"], tuning["order"])
+    pruned = {"ms_per_step": pdt * 1e3, "lookups_per_s": lookups / pdt,
+              "gather_kernel_ms": pprof["total_ms"] / max(pprof["launches"], 1),
+              "speedup_vs_full_scoring": ms_per_step / (pdt * 1e3),
+              "same_hits": bool(np.array_equal(pids, ids) and np.array_equal(pscores, sc)),
+              "steps": psteps}
+    log(f"pruned step: {pruned}")
+
     # plain path: one query per launch, same queries
     npq = min(args.plain_queries, qs.n)
     sub = qs.subset(range(npq))
@@ -511,9 +553,13 @@ def main():
     serving = None
     if args.serve_rates and args.config == 3:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
+        def set_prune(on):
+            ix.set_tuning(tuning["unroll"], tuning["chunk"], tuning["order"],
+                          prune=cobs.PRUNE_ON if on else cobs.PRUNE_OFF)
+
         serving = serve_measure(cobs, synth, torch, ix, rates, args.serve_pool,
                                 args.serve_seconds, args.serve_max, 100, args.serve_streams,
-                                set_launch)
+                                set_launch, set_prune)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -636,6 +682,7 @@ def main():
         "gather_row_bytes_per_launch": gather_bytes,
         "survivors_per_step": survivors,
         "topk100_ms_per_step": topk_ms,
+        "pruned": pruned,
         "plain_path": {"value": plain_rate, "unit": "lookups/s", "queries": npq,
                        "speedup_batched": value / plain_rate if plain_rate else None,
                        "direct_launches_value": plain_direct_rate,

@@ -517,15 +517,37 @@ typedef enum {
 } cobs_launch;
 
 /*
+ * Early exit of threshold queries.  A document's score is its count of the
+ * query's distinct terms whose rows hold its bit (section 2.2); after c of
+ * the l terms it can gain at most l - c more, so once every document of a
+ * block's column slice scores below T - (l - c), none of them can be
+ * reported.
+ *  COBS_PRUNE_OFF  every term is counted for every document (the scoring
+ *                  of the paper, which has no pruning);
+ *  COBS_PRUNE_ON   the gather checks every 64 terms and stops a (query,
+ *                  slice) work item as soon as no document of the slice can
+ *                  reach T.  Hits, scores and top-k are the same as with
+ *                  COBS_PRUNE_OFF: every document that reaches T is counted
+ *                  over every term.  Full score vectors (cobs_query_scores)
+ *                  and queries with T = 0 are never pruned, nor are launches
+ *                  whose slices are all at most 512 bytes wide (several terms
+ *                  per load).
+ */
+typedef enum {
+    COBS_PRUNE_OFF = 0,
+    COBS_PRUNE_ON = 1,
+} cobs_prune;
+
+/*
  * Launch shape of the gather kernel for an index: `unroll` terms whose rows
  * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4), `chunk`, the
  * most distinct terms per work item (longer queries are split and their
  * counts merged; a batch is split into about two work items per resident
  * wavefront, with items of at most `chunk` terms), `order` (cobs_order),
- * `host_reads` (cobs_host_reads; offloaded indexes only) and `launch`
- * (cobs_launch).  0 = defaults (8 or 2; 16384; COBS_ORDER_AUTO;
- * COBS_HOST_READS_AUTO; COBS_LAUNCH_AUTO).  Results never depend on any of
- * them.
+ * `host_reads` (cobs_host_reads; offloaded indexes only), `launch`
+ * (cobs_launch) and `prune` (cobs_prune).  0 = defaults (8 or 2; 16384;
+ * COBS_ORDER_AUTO; COBS_HOST_READS_AUTO; COBS_LAUNCH_AUTO; COBS_PRUNE_OFF).
+ * Results never depend on any of them.
  */
 typedef struct {
     uint32_t unroll;
@@ -534,6 +556,7 @@ typedef struct {
     uint32_t order;
     uint32_t host_reads;
     uint32_t launch;
+    uint32_t prune;
 } cobs_tuning;
 
 /* Time the gather kernel on the sample batch for every supported unroll and

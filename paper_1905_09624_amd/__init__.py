@@ -25,6 +25,7 @@ MODE_BATCHED, MODE_PLAIN = 0, 1
 ORDER_AUTO, ORDER_QUERIES, ORDER_SLICES = 0, 1, 2   # cobs_order: gather work-item order
 HOST_READS_AUTO, HOST_READS_STREAM, HOST_READS_IN_PLACE = 0, 1, 2   # cobs_host_reads
 LAUNCH_AUTO, LAUNCH_DIRECT = 0, 1   # cobs_launch: replayed graphs for single short queries or not
+PRUNE_OFF, PRUNE_ON = 0, 1          # cobs_prune: early exit of threshold queries (same results)
 
 
 class CobsError(RuntimeError):
@@ -77,7 +78,8 @@ class ServeStats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("unroll", C.c_uint32), ("chunk", C.c_uint32), ("gather_ms", C.c_double),
-                ("order", C.c_uint32), ("host_reads", C.c_uint32), ("launch", C.c_uint32)]
+                ("order", C.c_uint32), ("host_reads", C.c_uint32), ("launch", C.c_uint32),
+                ("prune", C.c_uint32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_uint64)
@@ -375,8 +377,8 @@ class Index:
         return dict(unroll=t.unroll, chunk=t.chunk, order=t.order, gather_ms=t.gather_ms)
 
     def set_tuning(self, unroll=0, chunk=0, order=ORDER_AUTO, host_reads=HOST_READS_AUTO,
-                   launch=LAUNCH_AUTO) -> None:
-        t = Tuning(unroll, chunk, 0.0, order, host_reads, launch)
+                   launch=LAUNCH_AUTO, prune=PRUNE_OFF) -> None:
+        t = Tuning(unroll, chunk, 0.0, order, host_reads, launch, prune)
         _check(lib().cobs_set_tuning(self._h, C.byref(t)))
 
     def query_flat(self, data, q_off, k=(4, 5), topk=0, score_bits=32, mode=MODE_BATCHED,

@@ -173,7 +173,23 @@ __global__ __launch_bounds__(256, (kH1 || P > 12) ? 1 : 4) void gather_kernel(Ga
         const uint64_t *hp = a.hashes + qn.hbase * a.h;
 
         cnt.clear();
+        // pruning (unpacked launches): after every 64 terms the item ends if
+        // every document of the slice scores below T minus the terms not yet
+        // counted (in this chunk or any other): none of them can reach T any
+        // more, and their partial counts stay below T, so the reported hits
+        // and scores do not change.  (A per-lane stop would also spare the
+        // lines of dead lanes in a live slice, but its predicated loads cost
+        // this kernel its fourth wavefront per SIMD.)
+        const bool prune = !kPacked && a.prune != 0;
         for (uint32_t k0 = kbeg; k0 < kend; k0 += 64) {
+            if (prune && k0 > kbeg) {
+                const uint32_t left = qn.ell - (k0 - kbeg);
+                if (qn.thr > left) {
+                    uint32_t g[4];
+                    cnt.ge(qn.thr - left, g);
+                    if (__ballot((g[0] | g[1] | g[2] | g[3]) != 0u) == 0) break;
+                }
+            }
             const uint32_t n = min(64u, kend - k0);
             uint32_t r[kH1 ? 1 : kMaxHashes];
             if (lane < n) {

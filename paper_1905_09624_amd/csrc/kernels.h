@@ -97,6 +97,9 @@ struct GatherArgs {
     // chunks in qorder order); 1 = slice-major (every chunk of one slice, in
     // qorder order, before the next slice)
     uint32_t slice_major;
+    // 1: documents that can no longer reach their query's threshold stop
+    // being counted (never with full_scores)
+    uint32_t prune;
 };
 
 // ---- query path ----------------------------------------------------------

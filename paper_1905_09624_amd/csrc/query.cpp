@@ -105,6 +105,12 @@ struct BatchPlan {
     size_t o_wb = 0, o_tb = 0, o_sl = 0, o_lq = 0, o_gq = 0, o_gp = 0, meta = 0;
 };
 
+// the batch's cobs_prune: its own, else the index's
+static uint32_t prune_of(const cobs_index *ix, const BatchSpec &b)
+{
+    return (b.prune < 0 ? ix->tuned_prune : (uint32_t)b.prune) == COBS_PRUNE_ON ? 1u : 0u;
+}
+
 cobs_status plan_batch(cobs_index *ix, const BatchSpec &b, BatchPlan &pl)
 {
     const uint32_t n = b.n;
@@ -390,8 +396,9 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
     const size_t inline_off = (head_bytes + 15) & ~size_t(15);
     COBS_HIP(ws.h_small.ensure(inline_off + 8 * (size_t)kGraphInlineHits));
 
+    const uint32_t prune = prune_of(ix, b);
     const std::vector<uint64_t> key = {
-        wclass, (uint64_t)pl.planes, (uint64_t)pl.unroll, pl.packed, pl.n_large, chunk, (uint64_t)grid,
+        wclass, (uint64_t)pl.planes, (uint64_t)pl.unroll, pl.packed, pl.n_large, chunk, (uint64_t)grid, prune,
         b.k_num, b.k_den, b.topk, ell_limit, order, b.slots != nullptr, pl.meta, pl.o_lq, ws.cand_cap,
         (uint64_t)ix->d_matrix, (uint64_t)ws.meta.p, (uint64_t)ws.terms.p, (uint64_t)ws.uterms.p,
         (uint64_t)ws.hashes.p, (uint64_t)ws.table.p, (uint64_t)ws.head.p, (uint64_t)ws.tickets.p,
@@ -454,6 +461,7 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
         ga.chunk = chunk;
         ga.topk = b.topk;
         ga.n_docs = ix->n_docs;
+        ga.prune = prune;
         ga.slice_major = order == COBS_ORDER_SLICES ? 1u : 0u;
         // three kernels: terms, set and plan in one workgroup; the gather; the
         // hits sorted where the gather wrote them
@@ -662,6 +670,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         ga.n_docs = ix->n_docs;
         const uint32_t order = b.order ? b.order : (ix->tuned_order ? ix->tuned_order : default_order(ix));
         ga.slice_major = order == COBS_ORDER_SLICES ? 1u : 0u;
+        ga.prune = full ? 0u : prune_of(ix, b);
         const bool prof = g_prof.load() != 0;
         const bool timed = prof || b.time_gather;
         if (timed) {
@@ -1149,11 +1158,13 @@ cobs_status cobs_set_tuning(cobs_index *ix, const cobs_tuning *t)
     if (t->order > COBS_ORDER_SLICES) return set_error(COBS_EINVAL, "unknown work-item order");
     if (t->host_reads > COBS_HOST_READS_IN_PLACE) return set_error(COBS_EINVAL, "unknown host_reads");
     if (t->launch > COBS_LAUNCH_DIRECT) return set_error(COBS_EINVAL, "unknown launch");
+    if (t->prune > COBS_PRUNE_ON) return set_error(COBS_EINVAL, "unknown prune");
     ix->tuned_unroll = (int)t->unroll;
     ix->tuned_chunk = t->chunk;
     ix->tuned_order = t->order;
     ix->tuned_host_reads = t->host_reads;
     ix->tuned_launch = t->launch;
+    ix->tuned_prune = t->prune;
     return COBS_OK;
 }
 
@@ -1166,7 +1177,7 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
     const uint32_t chunks[] = {0, 512, 1024, 2048, 4096, 8192, 16384, 1u << 20};
     Workspace *ws = acquire_workspace(ix);
     const uint32_t order0 = default_order(ix);
-    cobs_tuning win{0, 0, 1e300, order0, ix->tuned_host_reads, ix->tuned_launch};
+    cobs_tuning win{0, 0, 1e300, order0, ix->tuned_host_reads, ix->tuned_launch, ix->tuned_prune};
     cobs_status s = COBS_OK;
     auto time_shape = [&](int u, uint32_t c, uint32_t order) -> double {
         BatchSpec spec;
@@ -1179,6 +1190,7 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
         spec.unroll = (uint32_t)u;
         spec.chunk_cap = c;
         spec.order = order;
+        spec.prune = 0;   // shapes are timed over every term
         spec.time_gather = true;
         double t = 1e300;
         for (int rep = 0; rep < 2 && s == COBS_OK; ++rep) {   // first run warms up
@@ -1195,7 +1207,8 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
             const double t = time_shape(u, c, order0);
             if (s != COBS_OK) break;
             if (t < win.gather_ms)
-                win = cobs_tuning{(uint32_t)u, c, t, order0, ix->tuned_host_reads, ix->tuned_launch};
+                win = cobs_tuning{(uint32_t)u, c, t, order0, ix->tuned_host_reads, ix->tuned_launch,
+                                  ix->tuned_prune};
         }
         if (s != COBS_OK) break;
     }
@@ -1203,7 +1216,8 @@ cobs_status cobs_tune(cobs_index *ix, const uint8_t *bytes, const uint64_t *q_of
         const uint32_t other = order0 == COBS_ORDER_SLICES ? COBS_ORDER_QUERIES : COBS_ORDER_SLICES;
         const double t = time_shape((int)win.unroll, win.chunk, other);
         if (s == COBS_OK && t < win.gather_ms)
-            win = cobs_tuning{win.unroll, win.chunk, t, other, ix->tuned_host_reads, ix->tuned_launch};
+            win = cobs_tuning{win.unroll, win.chunk, t, other, ix->tuned_host_reads, ix->tuned_launch,
+                              ix->tuned_prune};
     }
     release_workspace(ix, ws);
     if (s != COBS_OK) return s;

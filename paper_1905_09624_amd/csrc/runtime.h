@@ -108,6 +108,7 @@ struct BatchSpec {
     uint32_t unroll = 0;               // terms in flight per wavefront; 0 = tuned or default
     uint32_t order = 0;                // cobs_order of the work items; 0 = tuned or by slice size
     uint32_t host_reads = 0;           // cobs_host_reads (offloaded index); 0 = tuned or automatic
+    int prune = -1;                    // cobs_prune; -1 = the index's setting
     uint32_t *full_scores = nullptr;   // host [n * n_docs]: full score mode
     uint64_t *terms_out = nullptr;     // host [windows]: terms-only mode
     const uint32_t *slots = nullptr;   // host [n]: score-buffer slot of each query in accum
@@ -151,6 +152,7 @@ struct cobs_index {
     uint8_t *h_dev_matrix = nullptr;   // device address of h_matrix (rows read in place)
     uint32_t tuned_host_reads = 0;     // cobs_tuning.host_reads
     uint32_t tuned_launch = 0;         // cobs_tuning.launch
+    uint32_t tuned_prune = 0;          // cobs_tuning.prune
     std::vector<Group> groups;
     cobs::SliceDesc *d_group_slices = nullptr;   // slices, base relative to their group
     uint8_t *d_stage[2] = {nullptr, nullptr};

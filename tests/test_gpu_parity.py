@@ -51,8 +51,8 @@ def rand_dna(rng, n, alphabet=b"ACGT"):
     return bytes(rng.choice(np.frombuffer(alphabet, np.uint8), size=n))
 
 
-def check_queries(gix, oix, data, off, k=(4, 5), topk=0, mode=0):
-    res = gix.query(data, off, k=k, topk=topk, mode=mode)
+def check_queries(gix, oix, data, off, k=(4, 5), topk=0, mode=0, chunk=0):
+    res = gix.query(data, off, k=k, topk=topk, mode=mode, chunk=chunk)
     for i in range(len(off) - 1):
         qb = data[int(off[i]):int(off[i + 1])].tobytes()
         ids, sc, l = oix.query(qb, k[0], k[1], topk)
@@ -254,6 +254,87 @@ def test_workload_full_scores(workload):
 def test_workload_hits(workload, k, topk, mode):
     w, d, qs, gix, oix = workload
     check_queries(gix, oix, qs.bytes, qs.q_off, k=k, topk=topk, mode=mode)
+
+
+# ---- early exit of threshold queries (cobs_prune) ----------------------------------
+# Pruning runs in unpacked launches only: an index with a block wider than
+# 4,096 documents (1 KiB row slices).
+
+@pytest.fixture(scope="module", params=["dna-h1", "bytes-h3"])
+def wide(request):
+    # 9,000 short documents in blocks of 8,192 (one 1 KiB slice and a narrow
+    # last block); queries: exact substrings of documents, substrings with 1%
+    # substitutions, random strings, and the empty query
+    cobs = _cobs()
+    rng = np.random.default_rng(31)
+    dna = request.param == "dna-h1"
+    gen = (lambda n: rand_dna(rng, n)) if dna else (lambda n: rng.integers(0, 256, n, np.uint8).tobytes())
+    docs = [[gen(int(rng.integers(40, 600)))] for _ in range(9000)]
+    kind, q, h, p = (0, 31, 1, 0.3) if dna else (1, 8, 3, 0.1)
+    gix, oix = build_both(oracle.Docs.from_lists(docs), kind, q, dna, h, p, 8192, 0xABC)
+    assert max(gix.block(b)["stride"] for b in range(gix.info()["n_blocks"])) == 1024
+    qs, src = [b""], [-1]
+    for i in range(60):
+        if i % 3 == 2:
+            qs.append(gen(int(rng.integers(q, 600))))
+            src.append(-1)
+            continue
+        j = int(rng.integers(0, len(docs)))
+        x = bytearray(docs[j][0])
+        L = int(rng.integers(min(len(x), 95), len(x) + 1))
+        a = int(rng.integers(0, len(x) - L + 1))
+        x = x[a:a + L]
+        if i % 3 == 1:
+            for t in np.nonzero(rng.random(len(x)) < 0.01)[0]:
+                x[t] = (b"ACGT"[(b"ACGT".index(x[t]) + 1) % 4]) if dna else (x[t] + 1) % 256
+        qs.append(bytes(x))
+        src.append(j if i % 3 == 0 else -1)
+    data, off = queries_of(qs)
+    return cobs, gix, oix, data, off, src
+
+
+@pytest.mark.parametrize("k,topk,chunk", [((4, 5), 0, 0), ((1, 2), 3, 0), ((4, 5), 0, 37),
+                                           ((9, 10), 5, 100), ((1, 1), 0, 0), ((1, 1), 0, 64),
+                                           ((0, 1), 10, 0)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_pruned_hits_equal_oracle(wide, k, topk, chunk, mode):
+    # the same hits, scores and top-k as the oracle with pruning on, whole
+    # queries and queries split into chunks of 37, 64 or 100 terms (their
+    # counts merged through the score buffer).  K = 1: T = l, so after c terms
+    # a document stays live only with a score of exactly c, and a document
+    # holding the whole query must still be found (an off-by-one in the bound
+    # would drop it)
+    cobs, gix, oix, data, off, src = wide
+    gix.set_tuning(prune=cobs.PRUNE_ON)
+    try:
+        check_queries(gix, oix, data, off, k=k, topk=topk, mode=mode, chunk=chunk)
+        if k == (1, 1):
+            got = gix.query(data, off, k=k, mode=mode, chunk=chunk)
+            for i, j in enumerate(src):
+                if j >= 0:
+                    assert j in set(got[i][0].tolist()), (i, j)
+    finally:
+        gix.set_tuning()
+
+
+def test_pruned_results_equal_unpruned(wide):
+    # pruning never changes a result, and full score vectors ignore it
+    cobs, gix, oix, data, off, src = wide
+    want = [gix.query(data, off, k=k, topk=t) for k, t in (((4, 5), 0), ((1, 2), 2))]
+    sc0 = gix.scores(data, off)
+    gix.set_tuning(prune=cobs.PRUNE_ON)
+    try:
+        got = [gix.query(data, off, k=k, topk=t) for k, t in (((4, 5), 0), ((1, 2), 2))]
+        sc1 = gix.scores(data, off)
+    finally:
+        gix.set_tuning()
+    for x, y in zip(want, got):
+        for u, v in zip(x, y):
+            assert np.array_equal(u[0], v[0]) and np.array_equal(u[1], v[1]) and u[2] == v[2]
+    assert np.array_equal(sc0[0], sc1[0]) and np.array_equal(sc0[1], sc1[1])
+    with pytest.raises(cobs.CobsError) as e:
+        gix.set_tuning(prune=2)
+    assert e.value.status == cobs.EINVAL
 
 
 def test_planted_source_never_missed(workload):
