@@ -17,6 +17,14 @@ namespace {
 
 // ---- a5-a8: gather / AND / ADD / threshold-or-top-k -------------------------------------
 
+// chunks of a query in the first of two pruning launches: ceil(nch * f / 256),
+// at least 1 (every chunk of an unsplit query)
+__device__ __forceinline__ uint32_t phase1_chunks(uint32_t nch, uint32_t f256)
+{
+    const uint64_t n1 = ((uint64_t)nch * f256 + 255u) >> 8;
+    return n1 < 1u ? 1u : (n1 > nch ? nch : (uint32_t)n1);
+}
+
 // full adder on 32 independent bit positions: a + b + c = s + 2 carry
 __device__ __forceinline__ void csa(uint32_t &s, uint32_t &carry, uint32_t a, uint32_t b, uint32_t c)
 {
@@ -117,6 +125,32 @@ struct Counter {
     }
 };
 
+// Whether any document of a split (query, slice) has a count of at least
+// need in its score buffer (lanes below L).  Layout: while l < 2^16, four
+// 16-bit counts per 64-bit word, 32 words per lane at i*L + lane; else one
+// 32-bit count per document, 128 per lane at i*L + lane.
+__device__ __forceinline__ bool any_count_reaches(const uint32_t *acc, uint32_t L, uint32_t lane,
+                                                  bool packed, uint32_t need)
+{
+    bool any = false;
+    if (lane >= L) return false;
+    if (packed) {
+        const unsigned long long *acc4 = (const unsigned long long *)acc;
+#pragma unroll 4
+        for (uint32_t i = 0; i < 32; ++i) {
+            const unsigned long long v = __hip_atomic_load(acc4 + i * L + lane, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) any |= ((uint32_t)(v >> (16 * j)) & 0xFFFFu) >= need;
+        }
+    } else {
+#pragma unroll 4
+        for (uint32_t i = 0; i < 128; ++i)
+            any |= __hip_atomic_load(acc + i * L + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+    }
+    return any;
+}
+
 // U: terms whose rows are in flight per wavefront (h rows each).  Kernels
 // with several hashes and at most 12 counter planes are held to 128 VGPRs
 // (4 wavefronts per SIMD instead of 3; no spills): the text index's gather,
@@ -150,8 +184,16 @@ __global__ __launch_bounds__(256, (kH1 || P > 12) ? 1 : 4) void gather_kernel(Ga
         const uint32_t chunk = c - a.chunk_prefix[rank];
         const QInfo qn = a.qinfo[qi];
         const SliceDesc sd = a.slices[sl];
+        // two launches for split queries under pruning: phase 1 takes the
+        // first n1 chunks of every query, phase 2 the others, which skip
+        // their terms where phase 1 found that no document of the slice can
+        // reach T any more
+        const uint32_t n1 = a.phase ? phase1_chunks(qn.nch, a.phase1_256) : qn.nch;
+        if (a.phase && (a.phase == 1) != (chunk < n1)) continue;
+        const bool dead = a.phase == 2 && __hip_atomic_load(&a.dead[(uint64_t)qi * a.n_slices + sl],
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         const uint32_t kbeg = chunk * a.chunk;
-        const uint32_t kend = min(qn.ell, kbeg + a.chunk);
+        const uint32_t kend = dead ? kbeg : min(qn.ell, kbeg + a.chunk);
         // uniform slice geometry in SGPRs
         const uint64_t sbase = bcast64(sd.base);
         const uint32_t sstride = uniform_u32(sd.stride);
@@ -317,12 +359,29 @@ __global__ __launch_bounds__(256, (kH1 || P > 12) ? 1 : 4) void gather_kernel(Ga
                 }
             }
             __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");   // adds done before the ticket
-            uint32_t *ticket = &a.tickets[(uint64_t)qi * a.n_slices + sl];
+            const uint64_t slot = (uint64_t)qi * a.n_slices + sl;
+            uint32_t *ticket = &a.tickets[slot];
             uint32_t tk = 0;
             if (lane == 0) tk = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tk = uniform_u32(tk);
-            if (tk != qn.nch - 1) continue;
-            if (lane == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tk != qn.nch - 1) {
+                // the last chunk of phase 1 (when phase 2 has chunks left):
+                // after the first n1 chunks' c1 terms a document can still
+                // gain l - c1; it marks the (query, slice) dead if no
+                // document can reach T
+                if (a.phase == 1 && tk == n1 - 1) {
+                    const uint64_t c1 = min((uint64_t)qn.ell, (uint64_t)n1 * a.chunk);
+                    const uint32_t left = qn.ell - (uint32_t)c1;
+                    if (qn.thr > left && __ballot(any_count_reaches(acc, L, lane, packed, qn.thr - left)) == 0 &&
+                        lane == 0)
+                        __hip_atomic_store(&a.dead[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                continue;
+            }
+            if (lane == 0) {
+                __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (a.phase == 2) __hip_atomic_store(&a.dead[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             cnt.clear();
             if (lane < L) {
                 if (packed) {

@@ -100,6 +100,13 @@ struct GatherArgs {
     // 1: documents that can no longer reach their query's threshold stop
     // being counted (never with full_scores)
     uint32_t prune;
+    // split queries under pruning run in two launches: 0 = one launch (every
+    // chunk); 1 = the first ceil(nch * phase1_256 / 256) chunks of every
+    // query, whose last one marks dead[q * n_slices + slice] when no document
+    // of the slice can reach T; 2 = the remaining chunks (a dead slice's
+    // skip their terms; the last chunk clears the mark)
+    uint32_t phase, phase1_256;
+    uint32_t *dead;                    // [n_queries * n_slices], zero; left zero after phase 2
 };
 
 // ---- query path ----------------------------------------------------------

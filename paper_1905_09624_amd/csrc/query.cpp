@@ -369,8 +369,8 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
     const size_t head_bytes = sizeof(Scalars) + 8 + 8;
     COBS_HIP(ws.head.ensure(head_bytes));
     if (ws.tickets_slots < n_slices || !ws.tickets.p) {
-        COBS_HIP(ws.tickets.ensure(n_slices * 4, true, st));
-        ws.tickets_slots = ws.tickets.cap / 4;
+        COBS_HIP(ws.tickets.ensure(n_slices * 8, true, st));   // tickets, then dead marks
+        ws.tickets_slots = ws.tickets.cap / 8;
     }
     COBS_HIP(ws.qinfo.ensure(sizeof(QInfo)));
     COBS_HIP(ws.chunk_prefix.ensure(8));
@@ -608,10 +608,12 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     }
 
     // a4-a8
+    // tickets, then the dead marks of two-launch pruning: n x n_slices each,
+    // zero on allocation and left zero by every launch
     const uint64_t tslots_need = (uint64_t)n * n_slices;
     if (ws.tickets_slots < tslots_need || !ws.tickets.p) {
-        COBS_HIP(ws.tickets.ensure(std::max<uint64_t>(tslots_need, 1) * 4, true, st));
-        ws.tickets_slots = ws.tickets.cap / 4;
+        COBS_HIP(ws.tickets.ensure(std::max<uint64_t>(tslots_need, 1) * 8, true, st));
+        ws.tickets_slots = ws.tickets.cap / 8;
     }
     COBS_HIP(ws.qinfo.ensure((size_t)n * sizeof(QInfo)));
     COBS_HIP(ws.chunk_prefix.ensure((size_t)(n + 1) * 4));
@@ -671,6 +673,19 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         const uint32_t order = b.order ? b.order : (ix->tuned_order ? ix->tuned_order : default_order(ix));
         ga.slice_major = order == COBS_ORDER_SLICES ? 1u : 0u;
         ga.prune = full ? 0u : prune_of(ix, b);
+        // pruning of split queries: where a query may be cut into chunks, the
+        // gather runs twice, first over the leading fraction f of every
+        // query's chunks, so that the second launch skips the slices where no
+        // document can reach T any more.  A document's count after c terms is
+        // near p c (p: the filter's false-positive rate, the bound for every
+        // block), so none can reach T = K l once (1 - p) c > (1 - K) l; f
+        // adds a margin of 0.1 to that point, and no split pays for f >= 0.9.
+        uint32_t phase1_256 = 0;
+        if (ga.prune && (uint64_t)pl.maxw > C && ix->prm.fpr < 1.0) {
+            const double f = (1.0 - (double)b.k_num / b.k_den) / (1.0 - ix->prm.fpr) + 0.1;
+            if (f < 0.9) phase1_256 = (uint32_t)std::ceil(std::max(f, 0.0) * 256.0);
+        }
+        ga.dead = ws.tickets.as<uint32_t>() + ws.tickets_slots;
         const bool prof = g_prof.load() != 0;
         const bool timed = prof || b.time_gather;
         if (timed) {
@@ -679,8 +694,19 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
             COBS_HIP(hipEventRecord(ws.ev[0], st));
         }
         if (pl.in_place) ga.matrix = ix->h_dev_matrix;
-        if (n_slices && (!ix->h_matrix || pl.in_place))
-            COBS_HIP(launch_gather(ga, planes, unroll, grid, packed, st));
+        if (n_slices && (!ix->h_matrix || pl.in_place)) {
+            if (phase1_256) {
+                GatherArgs g1 = ga;
+                g1.phase = 1;
+                g1.phase1_256 = phase1_256;
+                COBS_HIP(launch_gather(g1, planes, unroll, grid, packed, st));
+                COBS_HIP(launch_fill_u64((uint64_t *)&dsc->work_counter, 1, 0, st));
+                g1.phase = 2;
+                COBS_HIP(launch_gather(g1, planes, unroll, grid, packed, st));
+            } else {
+                COBS_HIP(launch_gather(ga, planes, unroll, grid, packed, st));
+            }
+        }
         if (n_slices && ix->h_matrix && !pl.in_place) {
             cobs_status gs = gather_streamed(ix, ws, ga, planes, unroll, grid, st);
             if (gs != COBS_OK) return gs;
@@ -780,8 +806,8 @@ cobs_status reserve_workspace(cobs_index *ix, Workspace &ws, uint64_t W, uint32_
     COBS_HIP(ws.head.ensure(sizeof(Scalars) + (size_t)n * 8 + (size_t)(n + 1) * 4));
     COBS_HIP(ws.table.ensure(std::max<uint64_t>(4 * W + n, 1) * 8));
     if (ws.tickets_slots < (uint64_t)n * n_slices || !ws.tickets.p) {
-        COBS_HIP(ws.tickets.ensure(std::max<uint64_t>((uint64_t)n * n_slices, 1) * 4, true, st));
-        ws.tickets_slots = ws.tickets.cap / 4;
+        COBS_HIP(ws.tickets.ensure(std::max<uint64_t>((uint64_t)n * n_slices, 1) * 8, true, st));
+        ws.tickets_slots = ws.tickets.cap / 8;   // tickets, then dead marks
     }
     COBS_HIP(ws.qinfo.ensure((size_t)n * sizeof(QInfo)));
     COBS_HIP(ws.chunk_prefix.ensure((size_t)(n + 1) * 4));

@@ -152,7 +152,11 @@ def test_offloaded_results_equal_oracle(which):
             sc, nt = ix.scores(data, off)
             for j in range(len(qs)):
                 assert nt[j] == want[j][1] and np.array_equal(sc[j], want[j][0]), (host_reads, j)
-            for k, topk, mode, chunk in (((4, 5), 0, 0, 0), ((1, 2), 0, 1, 0), ((0, 1), 5, 0, 7)):
+            # the last two: early exit of threshold queries (same results)
+            for k, topk, mode, chunk, prune in (((4, 5), 0, 0, 0, 0), ((1, 2), 0, 1, 0, 0),
+                                                ((0, 1), 5, 0, 7, 0), ((4, 5), 0, 0, 0, 1),
+                                                ((1, 2), 3, 1, 0, 1)):
+                ix.set_tuning(host_reads=host_reads, prune=prune)
                 got = ix.query(data, off, k=k, topk=topk, mode=mode, chunk=chunk)
                 for j, x in enumerate(qs):
                     ids, scores, l = oix.query(x, k[0], k[1], topk)
