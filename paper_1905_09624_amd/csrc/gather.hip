@@ -17,12 +17,15 @@ namespace {
 
 // ---- a5-a8: gather / AND / ADD / threshold-or-top-k -------------------------------------
 
-// chunks of a query in the first of two pruning launches: ceil(nch * f / 256),
-// at least 1 (every chunk of an unsplit query)
-__device__ __forceinline__ uint32_t phase1_chunks(uint32_t nch, uint32_t f256)
+// Chunks of a query in the first of two pruning launches: the fraction
+// f = f0 + fz / sqrt(l) of its nch chunks, rounded up, at least 1; all of
+// them (nothing left to prune) when f >= 0.9.
+__device__ __forceinline__ uint32_t phase1_chunks(uint32_t nch, uint32_t ell, float f0, float fz)
 {
-    const uint64_t n1 = ((uint64_t)nch * f256 + 255u) >> 8;
-    return n1 < 1u ? 1u : (n1 > nch ? nch : (uint32_t)n1);
+    const float f = f0 + fz * rsqrtf((float)(ell > 1u ? ell : 1u));
+    if (!(f < 0.9f)) return nch;
+    const uint32_t n1 = (uint32_t)ceilf(f * (float)nch);
+    return n1 < 1u ? 1u : (n1 > nch ? nch : n1);
 }
 
 // full adder on 32 independent bit positions: a + b + c = s + 2 carry
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(256, (kH1 || P > 12) ? 1 : 4) void gather_kernel(Ga
         // first n1 chunks of every query, phase 2 the others, which skip
         // their terms where phase 1 found that no document of the slice can
         // reach T any more
-        const uint32_t n1 = a.phase ? phase1_chunks(qn.nch, a.phase1_256) : qn.nch;
+        const uint32_t n1 = a.phase ? phase1_chunks(qn.nch, qn.ell, a.phase1_f0, a.phase1_fz) : qn.nch;
         if (a.phase && (a.phase == 1) != (chunk < n1)) continue;
         const bool dead = a.phase == 2 && __hip_atomic_load(&a.dead[(uint64_t)qi * a.n_slices + sl],
                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;

@@ -101,11 +101,13 @@ struct GatherArgs {
     // being counted (never with full_scores)
     uint32_t prune;
     // split queries under pruning run in two launches: 0 = one launch (every
-    // chunk); 1 = the first ceil(nch * phase1_256 / 256) chunks of every
-    // query, whose last one marks dead[q * n_slices + slice] when no document
-    // of the slice can reach T; 2 = the remaining chunks (a dead slice's
-    // skip their terms; the last chunk clears the mark)
-    uint32_t phase, phase1_256;
+    // chunk); 1 = the first ceil(nch * f) chunks of every query, f =
+    // phase1_f0 + phase1_fz / sqrt(l) (all of them when f >= 0.9), whose
+    // last one marks dead[q * n_slices + slice] when no document of the
+    // slice can reach T; 2 = the remaining chunks (a dead slice's skip their
+    // terms; the last chunk clears the mark)
+    uint32_t phase;
+    float phase1_f0, phase1_fz;
     uint32_t *dead;                    // [n_queries * n_slices], zero; left zero after phase 2
 };
 

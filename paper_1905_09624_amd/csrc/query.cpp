@@ -80,6 +80,8 @@ uint32_t auto_chunk(uint64_t W, uint32_t n_slices, int grid, uint32_t cap)
 // the grid best.
 constexpr uint64_t kSliceMajorBytes = 128ull << 20;
 
+constexpr uint32_t kPruneMinChunk = 2048;
+
 uint32_t default_order(const cobs_index *ix)
 {
     uint64_t biggest = 0;
@@ -109,6 +111,31 @@ struct BatchPlan {
 static uint32_t prune_of(const cobs_index *ix, const BatchSpec &b)
 {
     return (b.prune < 0 ? ix->tuned_prune : (uint32_t)b.prune) == COBS_PRUNE_ON ? 1u : 0u;
+}
+
+// Pruning of split queries runs the gather twice, first over the leading
+// fraction f of every query's chunks, so that the second launch skips the
+// slices where no document can reach T any more.  An unmatched document's
+// count after c terms is about binomial(c, p) (p: the filter's false-positive
+// rate, which bounds every block's), so none of a slice's 8,192 can reach
+// T = K l once (1 - p) c - (1 - K) l exceeds about 4.5 standard deviations,
+// sqrt(p (1 - p) c): f = f0 + fz / sqrt(l) with f0 = (1 - K) / (1 - p) and
+// fz = 4.5 sqrt(p f0 / (1 - p)).  Only speed depends on f; a query whose f
+// reaches 0.9 runs whole in the first launch.  f0 = 1, fz = 0: no pruning.
+static void prune_split(const cobs_index *ix, const BatchSpec &b, float &f0, float &fz)
+{
+    f0 = 1.f;
+    fz = 0.f;
+    const double p = ix->prm.fpr;
+    if (b.full_scores || !prune_of(ix, b) || !(p > 0.0 && p < 1.0)) return;
+    const double f0d = std::max(0.0, (1.0 - (double)b.k_num / b.k_den) / (1.0 - p));
+    f0 = (float)f0d;
+    fz = (float)(4.5 * std::sqrt(p * f0d / (1.0 - p)));
+}
+
+static float prune_fraction(float f0, float fz, uint64_t ell)
+{
+    return f0 + fz / std::sqrt((float)std::max<uint64_t>(ell, 1));
 }
 
 cobs_status plan_batch(cobs_index *ix, const BatchSpec &b, BatchPlan &pl)
@@ -197,6 +224,22 @@ cobs_status plan_batch(cobs_index *ix, const BatchSpec &b, BatchPlan &pl)
     int grid = gather_grid(pl.planes, unroll, (int)h, pl.packed);
     const uint32_t cap = b.chunk_cap ? b.chunk_cap : (ix->tuned_chunk ? ix->tuned_chunk : kDefaultChunkCap);
     pl.chunk = b.chunk ? b.chunk : auto_chunk(pl.W, n_slices, grid, cap);
+    if (!b.chunk && pl.maxw > pl.chunk && pl.chunk > kPruneMinChunk) {
+        // two pruning launches: a batch whose items were cut at the cap
+        // takes chunks of about f times its uncapped size, so that the first
+        // launch (about a fraction f of the terms) still fills the grid
+        // twice over and a slice left live for the second finishes in more,
+        // shorter items; never below kPruneMinChunk terms, where a chunk's
+        // score-buffer merge (up to 128 atomic adds per lane) would cost
+        // more than its row reads save
+        float f0, fz;
+        prune_split(ix, b, f0, fz);
+        const float f = prune_fraction(f0, fz, pl.maxw);
+        if (f < 0.9f) {
+            const uint64_t want = (uint64_t)(f * (float)auto_chunk(pl.W, n_slices, grid, ~0u));
+            pl.chunk = (uint32_t)std::max<uint64_t>(kPruneMinChunk, std::min<uint64_t>(pl.chunk, want));
+        }
+    }
     uint64_t items = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t nw = wbase[i + 1] - wbase[i];
@@ -673,18 +716,10 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         const uint32_t order = b.order ? b.order : (ix->tuned_order ? ix->tuned_order : default_order(ix));
         ga.slice_major = order == COBS_ORDER_SLICES ? 1u : 0u;
         ga.prune = full ? 0u : prune_of(ix, b);
-        // pruning of split queries: where a query may be cut into chunks, the
-        // gather runs twice, first over the leading fraction f of every
-        // query's chunks, so that the second launch skips the slices where no
-        // document can reach T any more.  A document's count after c terms is
-        // near p c (p: the filter's false-positive rate, the bound for every
-        // block), so none can reach T = K l once (1 - p) c > (1 - K) l; f
-        // adds a margin of 0.1 to that point, and no split pays for f >= 0.9.
-        uint32_t phase1_256 = 0;
-        if (ga.prune && (uint64_t)pl.maxw > C && ix->prm.fpr < 1.0) {
-            const double f = (1.0 - (double)b.k_num / b.k_den) / (1.0 - ix->prm.fpr) + 0.1;
-            if (f < 0.9) phase1_256 = (uint32_t)std::ceil(std::max(f, 0.0) * 256.0);
-        }
+        // pruning of split queries: two launches (prune_split)
+        float f0 = 1.f, fz = 0.f;
+        if ((uint64_t)pl.maxw > C) prune_split(ix, b, f0, fz);
+        const bool two_launches = prune_fraction(f0, fz, pl.maxw) < 0.9f;
         ga.dead = ws.tickets.as<uint32_t>() + ws.tickets_slots;
         const bool prof = g_prof.load() != 0;
         const bool timed = prof || b.time_gather;
@@ -695,10 +730,11 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         }
         if (pl.in_place) ga.matrix = ix->h_dev_matrix;
         if (n_slices && (!ix->h_matrix || pl.in_place)) {
-            if (phase1_256) {
+            if (two_launches) {
                 GatherArgs g1 = ga;
                 g1.phase = 1;
-                g1.phase1_256 = phase1_256;
+                g1.phase1_f0 = f0;
+                g1.phase1_fz = fz;
                 COBS_HIP(launch_gather(g1, planes, unroll, grid, packed, st));
                 COBS_HIP(launch_fill_u64((uint64_t *)&dsc->work_counter, 1, 0, st));
                 g1.phase = 2;
