@@ -294,13 +294,15 @@ def wide(request):
 
 
 @pytest.mark.parametrize("k,topk,chunk", [((4, 5), 0, 0), ((1, 2), 3, 0), ((4, 5), 0, 37),
-                                           ((9, 10), 5, 100), ((1, 1), 0, 0), ((1, 1), 0, 64),
-                                           ((0, 1), 10, 0)])
+                                           ((1, 2), 0, 37), ((9, 10), 5, 100), ((1, 1), 0, 0),
+                                           ((1, 1), 0, 64), ((0, 1), 10, 0)])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_pruned_hits_equal_oracle(wide, k, topk, chunk, mode):
     # the same hits, scores and top-k as the oracle with pruning on, whole
     # queries and queries split into chunks of 37, 64 or 100 terms (their
-    # counts merged through the score buffer).  K = 1: T = l, so after c terms
+    # counts merged through the score buffer; split queries run in two
+    # launches, and at K = 1/2 the shorter ones whole in the first).  K = 1:
+    # T = l, so after c terms
     # a document stays live only with a score of exactly c, and a document
     # holding the whole query must still be found (an off-by-one in the bound
     # would drop it)
