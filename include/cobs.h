@@ -323,7 +323,7 @@ cobs_status cobs_query_scores(cobs_index *ix, const uint8_t *bytes,
  * hash sets, hashes, plan, tickets, score buffers of split queries) is
  * carved out of one fixed scratch array of 64 MiB that the library holds on
  * each device it runs on until the process ends; a batch that needs more
- * fails with EBUDGET (8 (2 + h) bytes per window, up to 32 more per window
+ * fails with EBUDGET (8 (2 + h) bytes per window, up to 41 more per window
  * of queries longer than 12,288 windows, and 4 bytes per document for every
  * query longer than one work item).
  *  bytes     device memory: query i is bytes[q_off[i] .. q_off[i+1])

@@ -237,7 +237,9 @@ __device__ __forceinline__ bool set_insert(uint64_t *table, uint64_t cap, uint64
 // Windows [b, e) of one query: insert every valid term (term_at(w): the
 // term of window w, kInvalidTerm for an invalid DNA window); each wavefront
 // reserves output positions for its new terms with one atomic add on count.
-template <int kScope, typename TermAt>
+// kScope: the widest scope of the threads sharing the table; kCountScope:
+// that of the threads sharing count.
+template <int kScope, int kCountScope, typename TermAt>
 __device__ __forceinline__ void dedup_windows(uint64_t *table, uint64_t cap, uint64_t *flag,
                                               TermAt term_at, uint64_t w0, uint64_t b,
                                               uint64_t e, uint64_t *uterms, uint64_t *hashes,
@@ -262,7 +264,7 @@ __device__ __forceinline__ void dedup_windows(uint64_t *table, uint64_t cap, uin
         if (m == 0) continue;
         uint32_t pos0 = 0;
         if (lane == (uint32_t)__builtin_ctzll(m))
-            pos0 = __hip_atomic_fetch_add(count, (uint32_t)__popcll(m), __ATOMIC_RELAXED, kScope);
+            pos0 = __hip_atomic_fetch_add(count, (uint32_t)__popcll(m), __ATOMIC_RELAXED, kCountScope);
         pos0 = lane_u32(pos0, (uint32_t)__builtin_ctzll(m));
         if (fresh) {
             const uint64_t pos = w0 + pos0 + __popcll(m & ((1ull << lane) - 1ull));
@@ -281,8 +283,8 @@ __device__ __forceinline__ void dedup_range(uint64_t *table, uint64_t cap, uint6
                                             uint64_t e, uint64_t *uterms, uint64_t *hashes,
                                             TermSpec ts, const Seeds &seeds, uint32_t *count)
 {
-    dedup_windows<kScope>(table, cap, flag, [&](uint64_t w) { return terms[w0 + w]; }, w0, b, e,
-                          uterms, hashes, ts, seeds, count);
+    dedup_windows<kScope, kScope>(table, cap, flag, [&](uint64_t w) { return terms[w0 + w]; }, w0, b, e,
+                                  uterms, hashes, ts, seeds, count);
 }
 
 // One workgroup per query whose set fits in kSlots LDS slots (lds_q: those
@@ -310,13 +312,226 @@ __global__ __launch_bounds__(kThreads) void dedup_lds_kernel(const uint64_t *ter
     if (threadIdx.x == 0) nterms[qi] = lcount;
 }
 
-// Queries with a global table (cleared to kEmpty beforehand: cap slots plus
-// one flag word at tbase[i]), kDedupWindowsPerGroup windows per workgroup of
-// 1024 threads.  A query of one workgroup keeps its atomics at workgroup
-// scope (served by its XCD's L2) and counts in LDS; a longer one spreads over
-// several workgroups with device-scope atomics, counting into nterms (zeroed
-// by the extract kernel).  g_q: those queries; gprefix[j]: first workgroup of
-// g_q[j].
+// Queries longer than kLdsMaxWindows (g_q; gprefix[j]: first of the
+// dedup_groups(windows) workgroups of g_q[j], kDedupWindowsPerGroup windows
+// each).  Their windows are partitioned by hash into nb = min(4 x groups,
+// kMaxBuckets) buckets (about 4,096 windows each up to 16.8 M windows), and
+// every bucket dedups in an LDS table of its own: a term's windows all fall
+// into one bucket, so the buckets' sets are disjoint and together the
+// query's set.  Per query, at tbase[i] in the global table (all of it filled
+// with kEmpty beforehand):
+//   [0, cap]             a device hash table of cap = table_cap(windows)
+//                        slots and the flag word of the all-ones term, for a
+//                        query with a bucket of more than kBucketSlots
+//                        windows (a term repeated thousands of times, hashes
+//                        crafted to collide, or more than 33 M windows),
+//                        which dedups as before: several workgroups on the
+//                        device table;
+//   [cap + 1, + windows) its valid terms, bucket by bucket;
+//   then nb words        per bucket: kEmpty + its count while counting, then
+//                        count | offset << 32;
+//   then one word        1 when the query takes the device table;
+//   then groups x nb     32-bit words: where each workgroup's terms of each
+//                        bucket start within the bucket.
+// Counts of distinct terms go to nterms (zeroed by the extract kernel) with
+// device-scope atomics.
+constexpr uint32_t kMaxBuckets = 4096;
+constexpr uint32_t kBucketSlots = kLdsTableSlots / 2;   // 64 KiB LDS tables: two workgroups per CU
+
+struct GlobalQuery {
+    uint32_t qi, part;   // query, workgroup of the query
+    uint64_t w0, nw, cap, nb;
+    uint64_t *table, *sorted, *bucket, *mode;
+    uint32_t *base;      // this workgroup's nb words
+};
+
+__host__ __device__ __forceinline__ uint64_t bucket_count_for(uint64_t groups)
+{
+    return 4 * groups < kMaxBuckets ? 4 * groups : kMaxBuckets;
+}
+
+__device__ __forceinline__ GlobalQuery global_query(const uint64_t *wbase, const uint64_t *tbase,
+                                                   const uint32_t *g_q, const uint32_t *gprefix,
+                                                   uint32_t n_g, uint64_t *gtable, uint32_t group)
+{
+    GlobalQuery g;
+    const uint32_t j = bsearch_le(gprefix, n_g, group);
+    g.qi = g_q[j];
+    g.part = group - gprefix[j];
+    g.w0 = wbase[g.qi];
+    g.nw = wbase[g.qi + 1] - g.w0;
+    g.cap = table_cap(g.nw);
+    g.nb = bucket_count_for(gprefix[j + 1] - gprefix[j]);
+    g.table = gtable + tbase[g.qi];
+    g.sorted = g.table + g.cap + 1;
+    g.bucket = g.sorted + g.nw;
+    g.mode = g.bucket + g.nb;
+    g.base = (uint32_t *)(g.mode + 1) + (uint64_t)g.part * g.nb;
+    return g;
+}
+
+__device__ __forceinline__ bool counts_term(uint64_t t, const TermSpec &ts)
+{
+    return ts.kind == 1 || t != kInvalidTerm;
+}
+
+__device__ __forceinline__ uint32_t bucket_of(uint64_t t, const Seeds &seeds, uint64_t nb)
+{
+    return (uint32_t)(((mix64(t ^ seeds.s[0]) >> 32) * nb) >> 32);
+}
+
+// One workgroup of 1,024 per kDedupWindowsPerGroup windows: count each
+// bucket's terms in LDS, then reserve the workgroup's range of every bucket
+// with one device-scope add per bucket.
+__global__ __launch_bounds__(1024) void bucket_count_kernel(const uint64_t *terms, const uint64_t *wbase,
+                                                            const uint64_t *tbase, const uint32_t *g_q,
+                                                            const uint32_t *gprefix, uint32_t n_g,
+                                                            uint64_t *gtable, TermSpec ts, Seeds seeds)
+{
+    __shared__ uint32_t hist[kMaxBuckets];
+    const GlobalQuery g = global_query(wbase, tbase, g_q, gprefix, n_g, gtable, blockIdx.x);
+    for (uint32_t i = threadIdx.x; i < g.nb; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const uint64_t b = (uint64_t)g.part * kDedupWindowsPerGroup;
+    const uint64_t e = min(g.nw, b + kDedupWindowsPerGroup);
+    for (uint64_t w = b + threadIdx.x; w < e; w += blockDim.x) {
+        const uint64_t t = terms[g.w0 + w];
+        if (counts_term(t, ts)) atomicAdd(&hist[bucket_of(t, seeds, g.nb)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < g.nb; i += blockDim.x) {
+        const uint32_t c = hist[i];
+        uint32_t at = 0;
+        if (c)   // the word counts from kEmpty: kEmpty + n after n terms
+            at = (uint32_t)(__hip_atomic_fetch_add(&g.bucket[i], (uint64_t)c, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT) + 1ull);
+        g.base[i] = at;
+    }
+}
+
+// One workgroup per query: bucket offsets (exclusive scan of the counts),
+// and the device-table mode when a bucket is too large for an LDS table.
+__global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint64_t *wbase, const uint64_t *tbase,
+                                                           const uint32_t *g_q, const uint32_t *gprefix,
+                                                           uint32_t n_g, uint64_t *gtable)
+{
+    __shared__ uint32_t wsum[16];
+    __shared__ uint64_t carry;
+    __shared__ uint32_t big;
+    const GlobalQuery g = global_query(wbase, tbase, g_q, gprefix, n_g, gtable, gprefix[blockIdx.x]);
+    if (threadIdx.x == 0) { carry = 0; big = 0; }
+    __syncthreads();
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    for (uint64_t base = 0; base < g.nb; base += blockDim.x) {
+        const uint64_t i = base + threadIdx.x;
+        const uint32_t c = i < g.nb ? (uint32_t)(g.bucket[i] + 1ull) : 0u;   // kEmpty + count
+        if (c > kBucketSlots) big = 1;
+        const uint32_t x = wave_excl_scan(c);
+        if (lane == 63) wsum[wave] = x + c;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (uint32_t k = 0; k < blockDim.x / 64; ++k) {
+            if (k < wave) before += wsum[k];
+            total += wsum[k];
+        }
+        if (i < g.nb) g.bucket[i] = (uint64_t)c | ((carry + before + x) << 32);
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && big) *g.mode = 1;
+}
+
+// The count kernel's grid: place each term in its bucket (LDS cursors from
+// the bucket's offset plus the workgroup's start in it).
+__global__ __launch_bounds__(1024) void bucket_scatter_kernel(const uint64_t *terms, const uint64_t *wbase,
+                                                              const uint64_t *tbase, const uint32_t *g_q,
+                                                              const uint32_t *gprefix, uint32_t n_g,
+                                                              uint64_t *gtable, TermSpec ts, Seeds seeds)
+{
+    __shared__ uint32_t cursor[kMaxBuckets];
+    const GlobalQuery g = global_query(wbase, tbase, g_q, gprefix, n_g, gtable, blockIdx.x);
+    if (*g.mode == 1) return;
+    for (uint32_t i = threadIdx.x; i < g.nb; i += blockDim.x)
+        cursor[i] = (uint32_t)(g.bucket[i] >> 32) + g.base[i];
+    __syncthreads();
+    const uint64_t b = (uint64_t)g.part * kDedupWindowsPerGroup;
+    const uint64_t e = min(g.nw, b + kDedupWindowsPerGroup);
+    for (uint64_t w = b + threadIdx.x; w < e; w += blockDim.x) {
+        const uint64_t t = terms[g.w0 + w];
+        if (counts_term(t, ts)) g.sorted[atomicAdd(&cursor[bucket_of(t, seeds, g.nb)], 1u)] = t;
+    }
+}
+
+// Four workgroups of 1,024 per kDedupWindowsPerGroup windows, one per
+// bucket (those past nb return): the bucket's set in an LDS table, then one
+// device-scope add reserves its range of the query's distinct terms (the
+// buckets of a query would otherwise contend for one counter), and every
+// thread writes the terms of its run of table slots with their h hashes.
+__global__ __launch_bounds__(1024) void bucket_dedup_kernel(const uint64_t *wbase, const uint64_t *tbase,
+                                                            const uint32_t *g_q, const uint32_t *gprefix,
+                                                            uint32_t n_g, uint64_t *gtable, uint64_t *uterms,
+                                                            uint64_t *hashes, uint32_t *nterms, TermSpec ts,
+                                                            Seeds seeds)
+{
+    __shared__ uint64_t ltable[kBucketSlots];
+    __shared__ uint64_t lflag;
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t lbase;
+    const GlobalQuery g = global_query(wbase, tbase, g_q, gprefix, n_g, gtable, blockIdx.x >> 2);
+    const uint64_t k = 4ull * g.part + (blockIdx.x & 3u);
+    if (k >= g.nb || *g.mode == 1) return;
+    const uint64_t word = g.bucket[k];
+    const uint32_t count = (uint32_t)(word & 0xFFFFFFFFull);
+    const uint64_t start = word >> 32;
+    if (count == 0) return;
+    const uint32_t cap = (uint32_t)(table_cap(count) < kBucketSlots ? table_cap(count) : kBucketSlots);
+    if (threadIdx.x == 0) lflag = kEmpty;
+    for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) ltable[s] = kEmpty;
+    __syncthreads();
+    const uint64_t *src = g.sorted + start;
+    for (uint32_t w = threadIdx.x; w < count; w += blockDim.x) {
+        const uint64_t t = src[w];
+        if (t == kEmpty) lflag = 0;   // the all-ones term (text); every writer stores 0
+        else (void)set_insert<__HIP_MEMORY_SCOPE_WORKGROUP>(ltable, cap, t, mix64(t ^ seeds.s[0]) & (cap - 1));
+    }
+    __syncthreads();
+    const uint32_t per = (cap + blockDim.x - 1) / blockDim.x;
+    const uint32_t s0 = min(cap, threadIdx.x * per), s1 = min(cap, s0 + per);
+    const bool ones = threadIdx.x == 0 && lflag == 0;
+    uint32_t mine = ones ? 1u : 0u;
+    for (uint32_t s = s0; s < s1; ++s) mine += ltable[s] != kEmpty;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t x = wave_excl_scan(mine);
+    if (lane == 63) wsum[wave] = x + mine;
+    __syncthreads();
+    uint32_t before = x, total = 0;
+    for (uint32_t i = 0; i < blockDim.x / 64; ++i) {
+        if (i < wave) before += wsum[i];
+        total += wsum[i];
+    }
+    if (threadIdx.x == 0) lbase = __hip_atomic_fetch_add(&nterms[g.qi], total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    uint64_t pos = g.w0 + lbase + before;
+    auto put = [&](uint64_t t) {
+        uterms[pos] = t;
+#pragma unroll
+        for (int i = 0; i < kMaxHashes; ++i)
+            if (i < (int)ts.h) hashes[pos * ts.h + i] = mix64(t ^ seeds.s[i]);
+        ++pos;
+    };
+    if (ones) put(kEmpty);
+    for (uint32_t s = s0; s < s1; ++s) {
+        const uint64_t t = ltable[s];
+        if (t != kEmpty) put(t);
+    }
+}
+
+// Queries with a bucket of more than kBucketSlots windows: the device
+// table (cap slots plus the all-ones term's flag word), kDedupWindowsPerGroup
+// windows per workgroup of 1024 threads.  A query of one workgroup keeps its
+// atomics at workgroup scope (served by its XCD's L2) and counts in LDS; a
+// longer one spreads over several workgroups with device-scope atomics.
 __global__ __launch_bounds__(1024) void dedup_global_kernel(const uint64_t *terms, const uint64_t *wbase,
                                                             const uint64_t *tbase, const uint32_t *g_q,
                                                             const uint32_t *gprefix, uint32_t n_g,
@@ -325,25 +540,21 @@ __global__ __launch_bounds__(1024) void dedup_global_kernel(const uint64_t *term
                                                             TermSpec ts, Seeds seeds)
 {
     __shared__ uint32_t lcount;
-    const uint32_t j = bsearch_le(gprefix, n_g, blockIdx.x);
-    const uint32_t qi = g_q[j];
-    const uint32_t part = blockIdx.x - gprefix[j];
-    const uint64_t w0 = wbase[qi], nw = wbase[qi + 1] - w0;
-    const uint64_t cap = table_cap(nw);
-    uint64_t *table = gtable + tbase[qi];
-    if (nw <= kDedupWindowsPerGroup) {
+    const GlobalQuery g = global_query(wbase, tbase, g_q, gprefix, n_g, gtable, blockIdx.x);
+    if (*g.mode != 1) return;
+    if (g.nw <= kDedupWindowsPerGroup) {
         if (threadIdx.x == 0) lcount = 0;
         __syncthreads();
-        dedup_range<__HIP_MEMORY_SCOPE_WORKGROUP>(table, cap, table + cap, terms, w0, 0, nw,
-                                                     uterms, hashes, ts, seeds, &lcount);
+        dedup_range<__HIP_MEMORY_SCOPE_WORKGROUP>(g.table, g.cap, g.table + g.cap, terms, g.w0, 0, g.nw,
+                                                  uterms, hashes, ts, seeds, &lcount);
         __syncthreads();
-        if (threadIdx.x == 0) nterms[qi] = lcount;
+        if (threadIdx.x == 0) nterms[g.qi] = lcount;
         return;
     }
-    const uint64_t b = (uint64_t)part * kDedupWindowsPerGroup;
-    const uint64_t e = min(nw, b + kDedupWindowsPerGroup);
-    dedup_range<__HIP_MEMORY_SCOPE_AGENT>(table, cap, table + cap, terms, w0, b, e, uterms, hashes,
-                                             ts, seeds, &nterms[qi]);
+    const uint64_t b = (uint64_t)g.part * kDedupWindowsPerGroup;
+    const uint64_t e = min(g.nw, b + kDedupWindowsPerGroup);
+    dedup_range<__HIP_MEMORY_SCOPE_AGENT>(g.table, g.cap, g.table + g.cap, terms, g.w0, b, e, uterms,
+                                          hashes, ts, seeds, &nterms[g.qi]);
 }
 
 // ---- plan ------------------------------------------------------------------------------
@@ -467,7 +678,7 @@ __global__ __launch_bounds__(kThreads) void front_one_kernel(
     if (threadIdx.x == 0) { lcount = 0; lflag = kEmpty; }
     for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) ltable[s] = kEmpty;
     __syncthreads();
-    dedup_windows<__HIP_MEMORY_SCOPE_WORKGROUP>(
+    dedup_windows<__HIP_MEMORY_SCOPE_WORKGROUP, __HIP_MEMORY_SCOPE_WORKGROUP>(
         ltable, cap, &lflag,
         [&](uint64_t w) {
             bool ok;
@@ -915,6 +1126,14 @@ hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint
     if (n_g) {
         hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(table_slots, 256)), dim3(256), 0, st,
                            table, table_slots, kEmpty);
+        hipLaunchKernelGGL(bucket_count_kernel, dim3(g_groups), dim3(1024), 0, st, terms, wbase, tbase, g_q,
+                           gprefix, n_g, table, ts, seeds);
+        hipLaunchKernelGGL(bucket_scan_kernel, dim3(n_g), dim3(1024), 0, st, wbase, tbase, g_q, gprefix, n_g,
+                           table);
+        hipLaunchKernelGGL(bucket_scatter_kernel, dim3(g_groups), dim3(1024), 0, st, terms, wbase, tbase, g_q,
+                           gprefix, n_g, table, ts, seeds);
+        hipLaunchKernelGGL(bucket_dedup_kernel, dim3(4 * g_groups), dim3(1024), 0, st, wbase, tbase, g_q,
+                           gprefix, n_g, table, uterms, hashes, nterms, ts, seeds);
         hipLaunchKernelGGL(dedup_global_kernel, dim3(g_groups), dim3(1024), 0, st, terms, wbase,
                            tbase, g_q, gprefix, n_g, table, uterms, hashes, nterms, ts, seeds);
     }
@@ -923,7 +1142,11 @@ hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint
 
 uint64_t dedup_table_slots(uint64_t windows)
 {
-    return windows <= kLdsMaxWindows ? 0 : table_cap(windows) + 1;
+    if (windows <= kLdsMaxWindows) return 0;
+    // device table and its flag word, the terms by bucket, a word per
+    // bucket, the mode word, a 32-bit start per workgroup and bucket
+    const uint64_t groups = dedup_groups(windows), nb = bucket_count_for(groups);
+    return table_cap(windows) + 1 + windows + nb + 1 + (groups * nb + 1) / 2;
 }
 
 bool dedup_tiny_table(uint64_t windows) { return table_cap(windows) <= kLdsTinySlots; }

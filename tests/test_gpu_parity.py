@@ -133,8 +133,12 @@ def test_terms_and_dedup_match_oracle():
     d = oracle.Docs.from_lists([rand_dna(rng, 500)])
     prm = cobs.make_params(0, 31, True, 1, 0.3, 0, 1)
     gix = cobs.Index.build(prm, d.bytes, d.str_off, d.doc_str)
+    # the last three: longer than an LDS set (their windows partitioned by
+    # hash into LDS sets), one with a k-mer repeated past an LDS table's
+    # capacity in one partition (the device table instead)
     qs = [b"", b"ACGT", rand_dna(rng, 31), rand_dna(rng, 5000, b"ACGTN"),
-          rand_dna(rng, 200) * 5, b"acgtNNACGTAC" * 40, rand_dna(rng, 20000)]
+          rand_dna(rng, 200) * 5, b"acgtNNACGTAC" * 40, rand_dna(rng, 20000),
+          rand_dna(rng, 70000, b"ACGTN"), rand_dna(rng, 3000) + b"A" * 20000 + rand_dna(rng, 3000)]
     data, off = queries_of(qs)
     got = gix.terms(data, off, q=31)
     for i, s in enumerate(qs):
@@ -152,7 +156,10 @@ def test_bytes_terms_with_all_ones_term():
     # with the all-ones term in more than one of them
     long_q = (b"\xff" * 9000 + rng.integers(0, 256, 12000, dtype=np.uint8).tobytes()
               + b"\xff" * 9000)
-    qs = [b"\xff" * 20, b"\xff" * 9 + b"abc", b"xyz", long_q]
+    # and a query partitioned into LDS sets with the all-ones term in one
+    mid_q = (rng.integers(0, 256, 15000, dtype=np.uint8).tobytes() + b"\xff" * 40
+             + rng.integers(0, 256, 15000, dtype=np.uint8).tobytes())
+    qs = [b"\xff" * 20, b"\xff" * 9 + b"abc", b"xyz", long_q, mid_q]
     data, off = queries_of(qs)
     got = gix.terms(data, off, q=8)
     for i, s in enumerate(qs):
