@@ -127,9 +127,11 @@ hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const ui
 // distinct term; nterms[i] = l of query i (zeroed by launch_extract).  A query
 // whose set fits in LDS is one workgroup with an LDS table: lds_q lists the
 // n_tiny queries with dedup_tiny_table(windows), then n_small others with
-// dedup_small_table(windows), then n_large others.  A
-// larger one (listed in g_q) has dedup_table_slots(windows) global slots at
-// table + tbase[i] (cleared here) and dedup_groups(windows) workgroups;
+// dedup_small_table(windows), then n_large others.  A larger one (listed in
+// g_q) has dedup_table_slots(windows) global slots at table + tbase[i]
+// (cleared here) and dedup_groups(windows) workgroups of kDedupWindowsPerGroup
+// windows; its windows are partitioned by hash into LDS sets, or, when a
+// partition is too large for one, share a device table;
 // gprefix[j]: first workgroup of g_q[j], g_groups = gprefix[n_g];
 // table_slots: total global slots.
 hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint64_t *tbase,
@@ -141,7 +143,7 @@ hipError_t launch_dedup(const uint64_t *terms, const uint64_t *wbase, const uint
 bool dedup_tiny_table(uint64_t windows);       // LDS table of kLdsTinySlots slots or fewer
 bool dedup_small_table(uint64_t windows);      // LDS table of kLdsTableSlots / 2 slots or fewer
 uint64_t dedup_table_cap(uint64_t windows);    // hash-set capacity for a query (power of 2)
-uint64_t dedup_table_slots(uint64_t windows);  // global slots (0: LDS table)
+uint64_t dedup_table_slots(uint64_t windows);  // global slots (0: one LDS table)
 uint32_t dedup_groups(uint64_t windows);       // workgroups of the query
 // Per-query chunks, thresholds, score-buffer slots, work totals; zeroes
 // counters.
