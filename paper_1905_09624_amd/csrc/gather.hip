@@ -1,11 +1,11 @@
-// The gather kernel of the COBS query path (section 2.2 of the COBS paper),
-// steps a5-a8: persistent wavefronts take work items (query chunk, column
-// slice), fetch the h rows of every term of the chunk (one coalesced 1 KiB
-// line per row slice, or several terms per load for narrow slices), AND
-// them, add the surviving bits into bit-plane counters held in VGPRs, merge
-// the counts of split queries in a score buffer, and report each slice of a
-// query: full scores, or the documents reaching the threshold (top-k by a
-// bit-plane radix select).
+// The gather kernel of the COBS query path (section 2.2 of the COBS paper):
+// row gather, AND, ADD and report.  Persistent wavefronts take work items
+// (query chunk, column slice), fetch the h rows of every term of the chunk
+// (one coalesced 1 KiB line per row slice, or several terms per load for
+// narrow slices), AND them, add the surviving bits into bit-plane counters
+// held in VGPRs, merge the counts of split queries in a score buffer, and
+// report each slice of a query: full scores, or the documents reaching the
+// threshold (top-k by a bit-plane radix select).
 #include "kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -15,7 +15,7 @@
 namespace cobs {
 namespace {
 
-// ---- a5-a8: gather / AND / ADD / threshold-or-top-k -------------------------------------
+// ---- gather / AND / ADD / threshold-or-top-k ---------------------------------------------
 
 // Chunks of a query in the first of two pruning launches: the fraction
 // f = f0 + fz / sqrt(l) of its nch chunks, rounded up, at least 1; all of
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(256, (kH1 || P > 12) ? 1 : 4) void gather_kernel(Ga
             }
         }
 
-        // a8: report this slice of the query
+        // report this slice of the query
         uint32_t valid[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) {

@@ -113,7 +113,7 @@ struct GatherArgs {
 
 // ---- query path ----------------------------------------------------------
 
-// a1: one term per window of every query (kInvalidTerm for DNA windows with
+// Term extraction: one term per window of every query (kInvalidTerm for DNA windows with
 // a non-ACGT byte).  qstart[i]: first byte of query i; wbase[i]: first window;
 // the windows end at wbase[n_queries] (device), total_windows bounds it from
 // above and sets the grid.
@@ -123,7 +123,7 @@ hipError_t launch_extract(const uint8_t *bytes, const uint64_t *qstart, const ui
                           uint32_t n_queries, uint64_t total_windows, TermSpec ts,
                           uint64_t *terms, uint32_t *nterms, hipStream_t st);
 
-// a2+a3: per-query set of terms (hash-set dedup) and the h hashes of each
+// Per-query set of terms (hash-set dedup) and the h hashes of each
 // distinct term; nterms[i] = l of query i (zeroed by launch_extract).  A query
 // whose set fits in LDS is one workgroup with an LDS table: lds_q lists the
 // n_tiny queries with dedup_tiny_table(windows), then n_small others with
@@ -158,7 +158,7 @@ hipError_t launch_plan(const uint32_t *nterms, const uint64_t *wbase, const uint
                        unsigned long long *work_counter, unsigned long long *cand_counter,
                        uint32_t *qcount, uint32_t *flags, hipStream_t st);
 
-// a5-a8: persistent gather / AND / ADD / threshold-or-top-k kernel.
+// The persistent gather / AND / ADD / threshold-or-top-k kernel.
 // planes: counter planes (>= bits of the largest l); unroll: terms whose rows
 // are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4).  packed: every
 // slice of a.slices is at most kPackedSliceBytes wide, and 2, 4 or 8 terms
@@ -171,7 +171,7 @@ int gather_default_unroll(int h);
 bool gather_unroll_valid(int unroll, int h);
 int gather_grid(int planes, int unroll, int h, bool packed);   // persistent grid: CUs x resident blocks
 
-// a8+a9 ordering: group candidates by query and sort each query's segment by
+// Hit ordering: group candidates by query and sort each query's segment by
 // (score desc, input id asc); write the first min(count, topk) hits.
 hipError_t launch_group_sort(const uint64_t *cand_key, const uint32_t *cand_q,
                              const unsigned long long *n_cand, uint64_t cap,
@@ -181,7 +181,7 @@ hipError_t launch_group_sort(const uint64_t *cand_key, const uint32_t *cand_q,
                              uint32_t *out_n, uint32_t *out_id, uint32_t *out_score,
                              hipStream_t st);
 
-// A batch of one query of at most max_windows <= kLdsMaxWindows windows: a1-a3 and the plan in one workgroup (terms straight into an LDS
+// A batch of one query of at most max_windows <= kLdsMaxWindows windows: terms, set, hashes and the plan in one workgroup (terms straight into an LDS
 // set); the same outputs as launch_extract + launch_dedup + launch_plan with
 // n_queries = 1.  bytes: the query, 4-byte aligned, 64 readable bytes after.
 hipError_t launch_front_one(const uint8_t *bytes, const uint64_t *wbase, uint64_t max_windows,

@@ -104,7 +104,7 @@ __host__ __device__ __forceinline__ uint64_t table_cap(uint64_t n)
     return c;
 }
 
-// ---- a1: term extraction ------------------------------------------------------
+// ---- term extraction ----------------------------------------------------------
 
 // Each lane takes per_lane consecutive windows (a wavefront 64 x per_lane).
 // A lane's windows of one query span at most per_lane + q - 1 bytes; it
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void extract_kernel(const uint8_t *bytes, cons
     }
 }
 
-// ---- a2 + a3: per-query term set and hashes ----------------------------------------
+// ---- per-query term set and hashes ----------------------------------------------
 
 // 64-bit compare-and-swap at the given memory scope; returns the old value.
 template <int kScope>

@@ -299,7 +299,7 @@ MetaPtrs meta_ptrs(const BatchPlan &pl, const uint8_t *base, bool slots)
     return m;
 }
 
-// a1-a3: terms of every window, then each query's distinct terms and their
+// Terms of every window, then each query's distinct terms and their
 // hashes; nterms[i] = l of query i.
 hipError_t launch_front(const cobs_index *ix, const BatchPlan &pl, const MetaPtrs &mp,
                         const uint8_t *dbytes, uint64_t *terms, uint64_t *table, uint64_t *uterms,
@@ -632,7 +632,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
     }
     const uint8_t *dbytes = ws.bytes.as<uint8_t>();
 
-    // a1-a3
+    // terms, sets, hashes
     COBS_HIP(ws.terms.ensure(std::max<uint64_t>(W, 1) * 8));
     COBS_HIP(ws.uterms.ensure(std::max<uint64_t>(W, 1) * 8));
     COBS_HIP(ws.hashes.ensure(std::max<uint64_t>(W, 1) * 8 * h));
@@ -655,7 +655,7 @@ cobs_status run_batch(cobs_index *ix, Workspace &ws, const BatchSpec &b, hipStre
         return COBS_OK;
     }
 
-    // a4-a8
+    // gather and report
     // tickets, then the dead marks of two-launch pruning: n x n_slices each,
     // zero on allocation and left zero by every launch
     const uint64_t tslots_need = (uint64_t)n * n_slices;
