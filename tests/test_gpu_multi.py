@@ -87,6 +87,26 @@ def test_multi_equals_oracle_over_the_union(parts, k, topk, mode):
         assert np.array_equal(got[i][0], ids) and np.array_equal(got[i][1], sc), (i, k, topk)
 
 
+def test_multi_with_early_exit_equals_oracle(parts):
+    # every index with early exit on: the same union of hits
+    cobs, rng, docs, built = parts
+    qs, data, off = _queries(rng, docs)
+    ixs = [ix for ix, _ in built]
+    oixs = [o for _, o in built]
+    for ix in ixs:
+        ix.set_tuning(prune=cobs.PRUNE_ON)
+    try:
+        for k, topk, chunk in (((3, 4), 2, 0), ((4, 5), 0, 32)):
+            got = cobs.query_multi(ixs, data, off, k=k, topk=topk, chunk=chunk)
+            for i, q in enumerate(qs):
+                ids, sc, l = _want(oixs, q, k[0], k[1], topk)
+                assert got[i][2] == l, i
+                assert np.array_equal(got[i][0], ids) and np.array_equal(got[i][1], sc), (i, k, topk)
+    finally:
+        for ix in ixs:
+            ix.set_tuning()
+
+
 def test_multi_of_one_index_is_the_index(parts):
     cobs, rng, docs, built = parts
     qs, data, off = _queries(rng, docs)

@@ -44,6 +44,23 @@ def test_served_results_equal_batch_and_oracle(served):
         assert lat > 0
 
 
+def test_served_with_early_exit_equal_oracle(served):
+    # the server over an index with early exit on (batches of queries up to
+    # 20 kbp, split over chunks: two pruning launches): the oracle's hits
+    cobs, ix, qs, oix = served
+    ix.set_tuning(prune=cobs.PRUNE_ON)
+    try:
+        srv = cobs.Server(ix, num_streams=3, max_batch_queries=16)
+        tickets = [srv.submit(qs.get(i), k=(4, 5), topk=i % 3) for i in range(qs.n)]
+        got = [srv.wait(t) for t in tickets]
+        srv.stop()
+    finally:
+        ix.set_tuning()
+    for i, (ids, sc, l, lat) in enumerate(got):
+        w_ids, w_sc, wl = oix.query(qs.get(i), 4, 5, i % 3)
+        assert l == wl and np.array_equal(ids, w_ids) and np.array_equal(sc, w_sc), i
+
+
 def test_same_result_alone_and_in_a_mix(served):
     cobs, ix, qs, oix = served
     x = qs.get(0)
