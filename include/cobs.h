@@ -524,14 +524,20 @@ typedef enum {
  * reported.
  *  COBS_PRUNE_OFF  every term is counted for every document (the scoring
  *                  of the paper, which has no pruning);
- *  COBS_PRUNE_ON   the gather checks every 64 terms and stops a (query,
- *                  slice) work item as soon as no document of the slice can
- *                  reach T.  Hits, scores and top-k are the same as with
+ *  COBS_PRUNE_ON   a (query, slice) work item holding all of a query's
+ *                  terms checks every 64 terms and stops as soon as no
+ *                  document of the slice can reach T (not in launches whose
+ *                  slices are all at most 512 bytes wide, several terms per
+ *                  load).  A batch whose queries are split over several
+ *                  items gathers twice: first the leading chunks of every
+ *                  query, then the rest, skipping the (query, slice) pairs
+ *                  whose merged counts show that no document can reach T.
+ *                  Hits, scores and top-k are the same as with
  *                  COBS_PRUNE_OFF: every document that reaches T is counted
  *                  over every term.  Full score vectors (cobs_query_scores)
- *                  and queries with T = 0 are never pruned, nor are launches
- *                  whose slices are all at most 512 bytes wide (several terms
- *                  per load).
+ *                  and queries with T = 0 are never pruned; single short
+ *                  queries replayed as a graph (cobs_launch) prune only
+ *                  within their items.
  */
 typedef enum {
     COBS_PRUNE_OFF = 0,
