@@ -535,9 +535,7 @@ typedef enum {
  *                  Hits, scores and top-k are the same as with
  *                  COBS_PRUNE_OFF: every document that reaches T is counted
  *                  over every term.  Full score vectors (cobs_query_scores)
- *                  and queries with T = 0 are never pruned; single short
- *                  queries replayed as a graph (cobs_launch) prune only
- *                  within their items.
+ *                  and queries with T = 0 are never pruned.
  */
 typedef enum {
     COBS_PRUNE_OFF = 0,

@@ -519,7 +519,23 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
                                         ws.qorder.as<uint32_t>(), ws.chunk_prefix.as<uint32_t>(),
                                         &dsc->total_items, &dsc->work_counter, &dsc->cand_counter,
                                         ws.qcount.as<uint32_t>(), &dsc->flags, cs);
-        if (e == hipSuccess) e = launch_gather(ga, pl.planes, pl.unroll, grid, pl.packed, cs);
+        // pruning of a split query: two gathers (prune_split), the work
+        // counter cleared by a fill kernel between them
+        float f0 = 1.f, fz = 0.f;
+        if (wclass > chunk) prune_split(ix, b, f0, fz);
+        if (e == hipSuccess && prune_fraction(f0, fz, wclass) < 0.9f) {
+            GatherArgs g1 = ga;
+            g1.phase = 1;
+            g1.phase1_f0 = f0;
+            g1.phase1_fz = fz;
+            g1.dead = ws.tickets.as<uint32_t>() + ws.tickets_slots;
+            e = launch_gather(g1, pl.planes, pl.unroll, grid, pl.packed, cs);
+            if (e == hipSuccess) e = launch_fill_u64((uint64_t *)&dsc->work_counter, 1, 0, cs);
+            g1.phase = 2;
+            if (e == hipSuccess) e = launch_gather(g1, pl.planes, pl.unroll, grid, pl.packed, cs);
+        } else if (e == hipSuccess) {
+            e = launch_gather(ga, pl.planes, pl.unroll, grid, pl.packed, cs);
+        }
         if (e == hipSuccess)
             e = launch_sort_one(ws.cand_key.as<uint64_t>(), ws.seg_a.as<uint64_t>(), &dsc->cand_counter,
                                 ws.cand_cap, b.topk, d_out_start, d_out_n, ws.out_id.as<uint32_t>(),

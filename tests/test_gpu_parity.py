@@ -378,14 +378,15 @@ def test_single_queries_replayed_graphs_equal_direct_and_oracle(workload):
         strings.append((s * (L // max(len(s), 1) + 1))[:L])
     strings += base[:8]
     want = {}
-    for k, topk in (((4, 5), 0), ((0, 1), 5)):
+    # the last two with early exit: split queries gather twice in the graph
+    for k, topk, prune in (((4, 5), 0, 0), ((0, 1), 5, 0), ((4, 5), 0, 1), ((9, 10), 3, 1)):
         for rep in range(3):
             for x in strings:
                 data = np.frombuffer(x, np.uint8) if x else np.zeros(0, np.uint8)
                 off = np.array([0, len(x)], np.uint64)
                 got = {}
                 for launch in (cobs.LAUNCH_AUTO, cobs.LAUNCH_DIRECT):
-                    gix.set_tuning(launch=launch)
+                    gix.set_tuning(launch=launch, prune=prune)
                     got[launch] = gix.query(data, off, k=k, topk=topk)[0]
                 gix.set_tuning()
                 kk = (x, k, topk)
