@@ -194,10 +194,12 @@ hipError_t launch_front_one(const uint8_t *bytes, const uint64_t *wbase, uint64_
                             hipStream_t st);
 // The hits of a batch of one query, sorted in place in cand_key (tmp: as
 // many keys of scratch): out_start[0..1], out_n[0], out_id, out_score as
-// launch_group_sort writes them for n_queries = 1.
+// launch_group_sort writes them for n_queries = 1; the first inline_cap of
+// them also to inline_id and inline_score.
 hipError_t launch_sort_one(uint64_t *cand_key, uint64_t *tmp, const unsigned long long *n_cand,
                            uint64_t cap, uint32_t topk, uint32_t *out_start, uint32_t *out_n,
-                           uint32_t *out_id, uint32_t *out_score, hipStream_t st);
+                           uint32_t *out_id, uint32_t *out_score, uint32_t *inline_id,
+                           uint32_t *inline_score, uint32_t inline_cap, hipStream_t st);
 
 // ---- construction ------------------------------------------------------------
 

@@ -876,7 +876,9 @@ __global__ __launch_bounds__(1024) void sort_one_kernel(uint64_t *cand_key, uint
                                                         const unsigned long long *n_cand,
                                                         uint64_t cap, uint32_t topk,
                                                         uint32_t *out_start, uint32_t *out_n,
-                                                        uint32_t *out_id, uint32_t *out_score)
+                                                        uint32_t *out_id, uint32_t *out_score,
+                                                        uint32_t *inline_id, uint32_t *inline_score,
+                                                        uint32_t inline_cap)
 {
     __shared__ uint64_t s[kSortRun];
     const unsigned long long nc = *n_cand;
@@ -894,6 +896,10 @@ __global__ __launch_bounds__(1024) void sort_one_kernel(uint64_t *cand_key, uint
         const uint64_t v = src[i];
         out_id[i] = ~(uint32_t)v;
         out_score[i] = (uint32_t)(v >> 32);
+        if (i < inline_cap) {
+            inline_id[i] = ~(uint32_t)v;
+            inline_score[i] = (uint32_t)(v >> 32);
+        }
     }
 }
 
@@ -1183,7 +1189,7 @@ hipError_t launch_front_one(const uint8_t *bytes, const uint64_t *wbase, uint64_
 {
     if (max_windows > kLdsMaxWindows) return hipErrorInvalidValue;
     if (dedup_small_table(max_windows))
-        hipLaunchKernelGGL((front_one_kernel<kLdsTableSlots / 2, 256>), dim3(1), dim3(256), 0, st, bytes,
+        hipLaunchKernelGGL((front_one_kernel<kLdsTableSlots / 2, 1024>), dim3(1), dim3(1024), 0, st, bytes,
                            wbase, slot, uterms, hashes, nterms, ts, seeds, chunk, n_slices, k_num, k_den,
                            ell_limit, qinfo, qorder, chunk_prefix, total_items, work_counter,
                            cand_counter, qcount, flags);
@@ -1197,10 +1203,11 @@ hipError_t launch_front_one(const uint8_t *bytes, const uint64_t *wbase, uint64_
 
 hipError_t launch_sort_one(uint64_t *cand_key, uint64_t *tmp, const unsigned long long *n_cand,
                            uint64_t cap, uint32_t topk, uint32_t *out_start, uint32_t *out_n,
-                           uint32_t *out_id, uint32_t *out_score, hipStream_t st)
+                           uint32_t *out_id, uint32_t *out_score, uint32_t *inline_id,
+                           uint32_t *inline_score, uint32_t inline_cap, hipStream_t st)
 {
     hipLaunchKernelGGL(sort_one_kernel, dim3(1), dim3(1024), 0, st, cand_key, tmp, n_cand, cap, topk,
-                       out_start, out_n, out_id, out_score);
+                       out_start, out_n, out_id, out_score, inline_id, inline_score, inline_cap);
     return hipGetLastError();
 }
 

@@ -414,8 +414,12 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
     COBS_HIP(ws.uterms.ensure(wclass * 8));
     COBS_HIP(ws.hashes.ensure(wclass * 8 * h));
     COBS_HIP(ws.table.ensure(8));
+    // the head, then the first kGraphInlineHits ids and scores, copied back
+    // in one piece
     const size_t head_bytes = sizeof(Scalars) + 8 + 8;
-    COBS_HIP(ws.head.ensure(head_bytes));
+    const size_t inline_off = (head_bytes + 15) & ~size_t(15);
+    const size_t back_bytes = inline_off + 8 * (size_t)kGraphInlineHits;
+    COBS_HIP(ws.head.ensure(back_bytes));
     if (ws.tickets_slots < n_slices || !ws.tickets.p) {
         COBS_HIP(ws.tickets.ensure(n_slices * 8, true, st));   // tickets, then dead marks
         ws.tickets_slots = ws.tickets.cap / 8;
@@ -441,8 +445,7 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
     COBS_HIP(ws.seg_b.ensure(ws.cand_cap * 8));
     COBS_HIP(ws.out_id.ensure(std::max<uint64_t>(ws.cand_cap, kGraphInlineHits) * 4));
     COBS_HIP(ws.out_score.ensure(std::max<uint64_t>(ws.cand_cap, kGraphInlineHits) * 4));
-    const size_t inline_off = (head_bytes + 15) & ~size_t(15);
-    COBS_HIP(ws.h_small.ensure(inline_off + 8 * (size_t)kGraphInlineHits));
+    COBS_HIP(ws.h_small.ensure(back_bytes));
 
     const uint32_t prune = prune_of(ix, b);
     const std::vector<uint64_t> key = {
@@ -536,16 +539,13 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
         } else if (e == hipSuccess) {
             e = launch_gather(ga, pl.planes, pl.unroll, grid, pl.packed, cs);
         }
+        uint32_t *inline_id = (uint32_t *)(ws.head.as<uint8_t>() + inline_off);
         if (e == hipSuccess)
             e = launch_sort_one(ws.cand_key.as<uint64_t>(), ws.seg_a.as<uint64_t>(), &dsc->cand_counter,
                                 ws.cand_cap, b.topk, d_out_start, d_out_n, ws.out_id.as<uint32_t>(),
-                                ws.out_score.as<uint32_t>(), cs);
-        if (e == hipSuccess) e = hipMemcpyAsync(hs, ws.head.p, head_bytes, hipMemcpyDeviceToHost, cs);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hs + inline_off, ws.out_id.p, 4 * (size_t)kGraphInlineHits, hipMemcpyDeviceToHost, cs);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hs + inline_off + 4 * (size_t)kGraphInlineHits, ws.out_score.p,
-                               4 * (size_t)kGraphInlineHits, hipMemcpyDeviceToHost, cs);
+                                ws.out_score.as<uint32_t>(), inline_id, inline_id + kGraphInlineHits,
+                                kGraphInlineHits, cs);
+        if (e == hipSuccess) e = hipMemcpyAsync(hs, ws.head.p, back_bytes, hipMemcpyDeviceToHost, cs);
         hipGraph_t graph = nullptr;
         const hipError_t ee = hipStreamEndCapture(cs, &graph);
         if (e == hipSuccess) e = ee;
