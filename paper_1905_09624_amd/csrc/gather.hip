@@ -64,10 +64,15 @@ struct Counter {
         }
     }
 
-    // add U (1, 2, 4 or 8) indicator vectors
+    // add U (1, 2, 4, 8 or 16) indicator vectors
     template <int U>
     __device__ __forceinline__ void add(const u32x4 *x)
     {
+        if constexpr (U == 16) {
+            add<8>(x);
+            add<8>(x + 8);
+            return;
+        }
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             uint32_t xs[U];
@@ -86,7 +91,7 @@ struct Counter {
                 csa(H[1][d], e, H[1][d], t0, t1);
                 ripple(d, 2, e);
             } else {
-                static_assert(U == 8, "U must be 1, 2, 4 or 8");
+                static_assert(U == 8 || U == 16, "U must be 1, 2, 4, 8 or 16");
                 uint32_t t0, t1, t2, t3, u0, u1, e;
                 csa(H[0][d], t0, H[0][d], xs[0], xs[1]);
                 csa(H[0][d], t1, H[0][d], xs[2], xs[3]);
@@ -496,12 +501,19 @@ __global__ __launch_bounds__(256, (kH1 || P > 12) ? 1 : 4) void gather_kernel(Ga
     }
 }
 
-// Instantiated variants: h = 1 with 4 or 8 terms in flight, h > 1 with 2 or
-// 4 (each term then has h rows in flight).
+// Instantiated variants: h = 1 with 4 or 8 terms in flight (and 16 for the
+// unpacked kernel, which single short queries use), h > 1 with 2 or 4 (each
+// term then has h rows in flight).
 template <int P, bool kPacked>
 hipError_t launch_gather_pk(const GatherArgs &a, int unroll, int grid, hipStream_t st)
 {
     if (a.h == 1) {
+        if constexpr (!kPacked) {
+            if (unroll == 16) {
+                hipLaunchKernelGGL((gather_kernel<P, 16, true, false>), dim3(grid), dim3(256), 0, st, a);
+                return hipGetLastError();
+            }
+        }
         if (unroll == 8)
             hipLaunchKernelGGL((gather_kernel<P, 8, true, kPacked>), dim3(grid), dim3(256), 0, st, a);
         else
@@ -527,7 +539,9 @@ int occ_of_pk(int unroll, int h)
 {
     int blocks = 0;
     hipError_t e;
-    if (h == 1)
+    if (h == 1 && unroll == 16 && !kPacked)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 16, true, false>, 256, 0);
+    else if (h == 1)
         e = unroll == 8
                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 8, true, kPacked>, 256, 0)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gather_kernel<P, 4, true, kPacked>, 256, 0);

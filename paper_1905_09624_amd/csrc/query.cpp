@@ -396,11 +396,15 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
     const uint32_t n_slices = (uint32_t)ix->slices.size();
     uint64_t wclass = 64;
     while (wclass < pl.maxw) wclass <<= 1;
-    const uint32_t C = auto_chunk(wclass, wclass, n_slices, gather_grid(pl.planes, pl.unroll, (int)h, pl.packed),
+    // a lone query leaves most of the device idle, so its items are latency
+    // bound: with one hash and wide slices each wavefront keeps 16 row loads
+    // in flight instead of the batch's 8
+    const int unroll = (h == 1 && !pl.packed) ? 16 : pl.unroll;
+    const uint32_t C = auto_chunk(wclass, wclass, n_slices, gather_grid(pl.planes, unroll, (int)h, pl.packed),
                                   b.chunk_cap ? b.chunk_cap : (ix->tuned_chunk ? ix->tuned_chunk : kDefaultChunkCap));
     const uint32_t chunk = b.chunk ? b.chunk : C;
     const uint64_t items = (wclass + chunk - 1) / chunk * n_slices;
-    const int grid = (int)std::min<uint64_t>((uint64_t)gather_grid(pl.planes, pl.unroll, (int)h, pl.packed),
+    const int grid = (int)std::min<uint64_t>((uint64_t)gather_grid(pl.planes, unroll, (int)h, pl.packed),
                                              std::max<uint64_t>(1, (items + 3) / 4));
     const uint64_t ell_limit = b.score_bits == 16 ? 0xFFFFull : 0xFFFFFFFFull;
     const uint32_t order = b.order ? b.order : (ix->tuned_order ? ix->tuned_order : default_order(ix));
@@ -449,7 +453,7 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
 
     const uint32_t prune = prune_of(ix, b);
     const std::vector<uint64_t> key = {
-        wclass, (uint64_t)pl.planes, (uint64_t)pl.unroll, pl.packed, pl.n_large, chunk, (uint64_t)grid, prune,
+        wclass, (uint64_t)pl.planes, (uint64_t)unroll, pl.packed, pl.n_large, chunk, (uint64_t)grid, prune,
         b.k_num, b.k_den, b.topk, ell_limit, order, b.slots != nullptr, pl.meta, pl.o_lq, ws.cand_cap,
         (uint64_t)ix->d_matrix, (uint64_t)ws.meta.p, (uint64_t)ws.terms.p, (uint64_t)ws.uterms.p,
         (uint64_t)ws.hashes.p, (uint64_t)ws.table.p, (uint64_t)ws.head.p, (uint64_t)ws.tickets.p,
@@ -532,12 +536,12 @@ static cobs_status run_single_replayed(cobs_index *ix, Workspace &ws, const Batc
             g1.phase1_f0 = f0;
             g1.phase1_fz = fz;
             g1.dead = ws.tickets.as<uint32_t>() + ws.tickets_slots;
-            e = launch_gather(g1, pl.planes, pl.unroll, grid, pl.packed, cs);
+            e = launch_gather(g1, pl.planes, unroll, grid, pl.packed, cs);
             if (e == hipSuccess) e = launch_fill_u64((uint64_t *)&dsc->work_counter, 1, 0, cs);
             g1.phase = 2;
-            if (e == hipSuccess) e = launch_gather(g1, pl.planes, pl.unroll, grid, pl.packed, cs);
+            if (e == hipSuccess) e = launch_gather(g1, pl.planes, unroll, grid, pl.packed, cs);
         } else if (e == hipSuccess) {
-            e = launch_gather(ga, pl.planes, pl.unroll, grid, pl.packed, cs);
+            e = launch_gather(ga, pl.planes, unroll, grid, pl.packed, cs);
         }
         uint32_t *inline_id = (uint32_t *)(ws.head.as<uint8_t>() + inline_off);
         if (e == hipSuccess)
