@@ -251,8 +251,16 @@ cobs_status plan_batch(cobs_index *ix, const BatchSpec &b, BatchPlan &pl)
         if (nw > pl.chunk) pl.pslots += 1;   // may be split: one score buffer
         items += (nw + pl.chunk - 1) / pl.chunk;
     }
-    // no more wavefronts than work items (4 per workgroup)
     items *= n_slices;
+    // fewer items than resident wavefronts leave the device partly idle and
+    // the items latency bound: with one hash and wide slices, 16 row loads
+    // in flight per wavefront instead of 8 (the tuned unroll stays for
+    // batches that fill the device)
+    if (!b.unroll && h == 1 && !pl.packed && items < (uint64_t)grid * 4) {
+        pl.unroll = unroll = 16;
+        grid = gather_grid(pl.planes, unroll, (int)h, false);
+    }
+    // no more wavefronts than work items (4 per workgroup)
     if ((uint64_t)grid * 4 > items) grid = (int)std::max<uint64_t>(1, (items + 3) / 4);
     pl.grid = grid;
 
