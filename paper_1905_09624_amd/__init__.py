@@ -378,6 +378,8 @@ class Index:
 
     def set_tuning(self, unroll=0, chunk=0, order=ORDER_AUTO, host_reads=HOST_READS_AUTO,
                    launch=LAUNCH_AUTO, prune=PRUNE_OFF) -> None:
+        """cobs_set_tuning: every field at once (0 = default); results never
+        depend on any of them."""
         t = Tuning(unroll, chunk, 0.0, order, host_reads, launch, prune)
         _check(lib().cobs_set_tuning(self._h, C.byref(t)))
 
