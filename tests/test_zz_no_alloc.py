@@ -38,8 +38,9 @@ def _noalloc(torch, ix, data, off, nd):
 def test_noalloc_scores_equal_allocating_entry_point_twice():
     torch, cobs = _setup()
     # 400 documents in blocks of 32 (13 blocks), queries long enough to be
-    # split into several work items (tickets, score buffers), plus an empty
-    # query and one shorter than q
+    # split into several work items (tickets, score buffers), two longer than
+    # an LDS set (their windows deduplicated in hash partitions), plus an
+    # empty query and one shorter than q
     w = synth.CONFIGS[3].scaled(250, "noalloc")
     d = synth.docs(w)
     prm = cobs.make_params(cobs.DNA, w.q, w.canonical, w.h, w.p, w.B, w.hash_seed)
@@ -48,7 +49,9 @@ def test_noalloc_scores_equal_allocating_entry_point_twice():
     oix = oracle.OracleIndex(oracle.Docs(d.bytes, d.str_off, d.doc_str), kind=oracle.DNA, q=w.q,
                              canonical=w.canonical, h=w.h, p=w.p, B=w.B, seed=w.hash_seed)
     qs = synth.dna_queries(w, n=40)
-    strings = [qs.get(i) for i in range(qs.n)] + [b"", b"ACGT" * 5]
+    rng = np.random.default_rng(77)
+    longs = [rng.choice(np.frombuffer(b"ACGT", np.uint8), n).tobytes() for n in (20000, 30000)]
+    strings = [qs.get(i) for i in range(qs.n)] + longs + [b"", b"ACGT" * 5]
     for call, subset in enumerate([strings, strings[3:11] + strings[-2:]]):
         data = np.frombuffer(b"".join(subset), np.uint8).copy()
         off = np.zeros(len(subset) + 1, np.uint64)
