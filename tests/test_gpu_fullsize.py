@@ -25,7 +25,7 @@ documents one at a time (oracle.QuerySet.doc_scores) and checks:
   vectors, the K = 4/5 hits restricted to those documents, and the top-100
   lists (consistent with the full scores, which are checked on those
   documents) must match.  With early exit of threshold queries (cobs_prune)
-  the K = 4/5 hits must equal the unpruned hits for every document.
+  the K = 4/5 and K = 1 hits must equal the unpruned hits for every document.
 * serving at full size (the compact 100k index): requests of the serving
   mix (31 bp to 1 Mbp), replayed as Poisson arrivals through a 4-stream
   server, get the batch path's hits, whose scores match the oracle on the
@@ -225,11 +225,15 @@ def _check_full_size(w, ix, docs, whole, per_block, queries, shapes, rng, topk=0
     ix.set_tuning(0, 0)
     hits = ix.query(data, off, k=w.k)
     top = ix.query(data, off, k=(0, 1), topk=topk) if topk else None
-    # early exit of threshold queries: the same hits for every document
+    # early exit of threshold queries: the same hits for every document, at
+    # the workload's K and at K = 1 (T = l: only documents holding every
+    # term counted so far stay live)
+    full1 = ix.query(data, off, k=(1, 1))
     ix.set_tuning(prune=1)
     phits = ix.query(data, off, k=w.k)
+    pfull1 = ix.query(data, off, k=(1, 1))
     ix.set_tuning(0, 0)
-    for qi, (a, b) in enumerate(zip(hits, phits)):
+    for qi, (a, b) in enumerate(list(zip(hits, phits)) + list(zip(full1, pfull1))):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2], qi
     _log(f"{w.name}: GPU scores of {len(queries)} queries in {len(shapes)} launch shapes")
     qset = oracle.QuerySet(queries, kind=_kind(w), q=w.q, canonical=w.canonical, h=w.h, p=w.p,
