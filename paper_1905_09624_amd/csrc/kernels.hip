@@ -425,7 +425,7 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint64_t *wbase
     for (uint64_t base = 0; base < g.nb; base += blockDim.x) {
         const uint64_t i = base + threadIdx.x;
         const uint32_t c = i < g.nb ? (uint32_t)(g.bucket[i] + 1ull) : 0u;   // kEmpty + count
-        if (c > kBucketSlots) big = 1;
+        if (c > kBucketSlots) atomicOr(&big, 1u);
         const uint32_t x = wave_excl_scan(c);
         if (lane == 63) wsum[wave] = x + c;
         __syncthreads();
@@ -492,7 +492,8 @@ __global__ __launch_bounds__(1024) void bucket_dedup_kernel(const uint64_t *wbas
     const uint64_t *src = g.sorted + start;
     for (uint32_t w = threadIdx.x; w < count; w += blockDim.x) {
         const uint64_t t = src[w];
-        if (t == kEmpty) lflag = 0;   // the all-ones term (text); every writer stores 0
+        if (t == kEmpty)   // the all-ones term (text)
+            __hip_atomic_store(&lflag, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else (void)set_insert<__HIP_MEMORY_SCOPE_WORKGROUP>(ltable, cap, t, mix64(t ^ seeds.s[0]) & (cap - 1));
     }
     __syncthreads();
