@@ -544,9 +544,9 @@ typedef enum {
 
 /*
  * Launch shape of the gather kernel for an index: `unroll` terms whose rows
- * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4; with 0, a batch
- * of one hash and wide slices with fewer work items than resident
- * wavefronts, a lone short query among them, uses 16), `chunk`, the
+ * are in flight per wavefront (h = 1: 4 or 8; h > 1: 2 or 4; a batch of one
+ * hash and wide slices with fewer work items than resident wavefronts, a
+ * lone short query among them, uses 16 whatever the setting), `chunk`, the
  * most distinct terms per work item (longer queries are split and their
  * counts merged; a batch is split into about two work items per resident
  * wavefront, with items of at most `chunk` terms), `order` (cobs_order),
